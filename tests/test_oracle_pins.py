@@ -1,0 +1,317 @@
+"""The CPU oracle against what the paper and the mathematics fix.
+
+None of these checks uses the oracle to check itself: every expected value
+comes from a closed form, from exhaustive enumeration, from an independent
+maximum-independent-set search, from Koenig's theorem through scipy's
+bipartite matching, or from a tree dynamic program (tests/pins.py).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2512_18334_amd import graphgen as gg
+from tests import pins
+from tests.helpers import assert_cover
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def check_mvc(orc, g, expected):
+    r = orc.mvc(g)
+    assert r["size"] == expected, (g.name, r["size"], expected)
+    assert_cover(g, r["cover"], size=expected)
+    return r
+
+
+def check_pvc_threshold(orc, g, mvc):
+    for k in range(max(0, mvc - 2), mvc + 3):
+        r = orc.pvc(g, k)
+        assert r["yes"] == (k >= mvc), (g.name, k, mvc, r["yes"])
+        if r["yes"]:
+            assert_cover(g, r["cover"], at_most=k)
+        else:
+            assert r["cover"].size == 0
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("n", list(range(1, 40)))
+def test_path(orc, n):
+    check_mvc(orc, gg.path(n), n // 2)
+
+
+@pytest.mark.parametrize("n", list(range(3, 40)))
+def test_cycle(orc, n):
+    # a chordless cycle needs ceil(n/2) (component rule, Sec. III-D)
+    check_mvc(orc, gg.cycle(n), (n + 1) // 2)
+
+
+@pytest.mark.parametrize("n", list(range(1, 16)))
+def test_clique(orc, n):
+    # a clique needs all but one vertex (component rule, Sec. III-D)
+    check_mvc(orc, gg.complete(n), max(n - 1, 0))
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 7), (2, 2), (3, 5), (4, 4),
+                                 (5, 9), (7, 3), (8, 8)])
+def test_complete_bipartite(orc, a, b):
+    check_mvc(orc, gg.complete_bipartite(a, b), min(a, b))
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 30])
+def test_star(orc, k):
+    check_mvc(orc, gg.star(k), 1)
+
+
+def test_petersen(orc):
+    check_mvc(orc, gg.petersen(), 6)
+
+
+@pytest.mark.parametrize("a,b", [(2, 2), (3, 3), (4, 5), (5, 7), (6, 6)])
+def test_grid(orc, a, b):
+    # bipartite with a (near-)perfect matching: floor(ab/2)
+    check_mvc(orc, gg.grid(a, b), (a * b) // 2)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
+def test_hypercube(orc, d):
+    check_mvc(orc, gg.hypercube(d), 1 << (d - 1))
+
+
+def test_fig1_example(orc):
+    # Sec. II-B worked example: minimum cover {b, e, h}; a..i are 0..8
+    g = gg.fig1_tree()
+    r = check_mvc(orc, g, 3)
+    assert sorted(r["cover"].tolist()) == [1, 4, 7]
+    # removing e leaves components {a,b,c} and {g,h,i}
+    check_pvc_threshold(orc, g, 3)
+
+
+def test_empty_and_edgeless(orc):
+    for g in [gg.from_edges(0, [], []), gg.from_edges(1, [], []),
+              gg.from_edges(17, [], [])]:
+        check_mvc(orc, g, 0)
+        r = orc.pvc(g, 0)
+        assert r["yes"] and r["cover"].size == 0
+
+
+def test_disjoint_union_adds(orc):
+    # Sec. III-A: the MVC of a disconnected graph combines its components'
+    parts = [gg.cycle(7), gg.complete(5), gg.petersen(), gg.path(6),
+             gg.gnp(14, 0.3, 11), gg.complete_bipartite(3, 4)]
+    expect = [4, 4, 6, 3, pins.brute_force_mvc(parts[4]), 3]
+    g = gg.relabel(gg.disjoint_union(parts), 5)
+    check_mvc(orc, g, sum(expect))
+
+
+# ------------------------------------------------------------- brute force
+
+def _all_graphs(n):
+    pairs = list(itertools.combinations(range(n), 2))
+    for mask in range(1 << len(pairs)):
+        e = [p for i, p in enumerate(pairs) if mask >> i & 1]
+        arr = np.array(e, dtype=np.int64).reshape(-1, 2)
+        yield gg.from_edges(n, arr[:, 0], arr[:, 1], f"all{n}_{mask}")
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_every_graph_up_to_5_vertices(orc, n):
+    for g in _all_graphs(n):
+        bf = pins.brute_force_mvc(g)
+        check_mvc(orc, g, bf)
+        r = orc.pvc(g, max(bf - 1, 0))
+        assert r["yes"] == (bf == 0)
+
+
+def test_random_graphs_bruteforce(orc):
+    r = gg.rng(20240)
+    for i in range(1200):
+        n = int(r.integers(6, 15))
+        p = float(r.uniform(0.1, 0.8))
+        g = gg.gnp(n, p, 1000 + i)
+        bf = pins.brute_force_mvc(g)
+        check_mvc(orc, g, bf)
+        if i % 10 == 0:
+            check_pvc_threshold(orc, g, bf)
+
+
+@pytest.mark.parametrize("n,p,seed", [(18, 0.2, 1), (20, 0.15, 2), (20, 0.3, 3),
+                                      (22, 0.12, 4), (24, 0.1, 5)])
+def test_bruteforce_up_to_24(orc, n, p, seed):
+    g = gg.gnp(n, p, seed)
+    check_mvc(orc, g, pins.brute_force_mvc(g))
+
+
+# ---------------------------------------------------------- bitset MIS pin
+
+@pytest.mark.parametrize("seed", list(range(1, 257)))
+def test_gnp60_vs_independent_set(orc, seed):
+    # the 60-vertex Erdos-Renyi workload, seeds 1..256
+    g = gg.config1_gnp60(seed)
+    mvc = g.n - pins.mis_bitset(g)
+    check_mvc(orc, g, mvc)
+    if seed <= 16:
+        check_pvc_threshold(orc, g, mvc)
+
+
+@pytest.mark.parametrize("n,p,seed", [(40, 0.15, 7), (50, 0.08, 8),
+                                      (64, 0.06, 9), (30, 0.4, 10)])
+def test_denser_vs_independent_set(orc, n, p, seed):
+    g = gg.gnp(n, p, seed)
+    check_mvc(orc, g, g.n - pins.mis_bitset(g))
+
+
+# ------------------------------------------------------------- Koenig pins
+
+@pytest.mark.parametrize("seed", list(range(12)))
+def test_random_bipartite_koenig(orc, seed):
+    r = gg.rng(500 + seed)
+    a, b = int(r.integers(5, 70)), int(r.integers(5, 70))
+    p = float(r.uniform(0.01, 0.08))
+    keep = r.random((a, b)) < p
+    ii, jj = np.nonzero(keep)
+    g = gg.relabel(gg.from_edges(a + b, ii, jj + a), seed)
+    left = pins.bipartition(g)
+    check_mvc(orc, g, pins.koenig_mvc(g, left))
+
+
+def test_bipartite_planted_chung_lu_koenig(orc):
+    # the bipartite variant of the planted power-law workload: every edge
+    # joins S to V \ S
+    g = gg.chung_lu_planted(60_000, 300_000, 2.1, 3_600, seed=33,
+                            bipartite=True)
+    left = np.zeros(g.n, bool)
+    left[g.planted] = True
+    expect = pins.koenig_mvc(g, left)
+    assert expect <= g.planted.size
+    r = check_mvc(orc, g, expect)
+    check_pvc_threshold(orc, g, r["size"])
+
+
+# --------------------------------------------------------------- tree DP pin
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (10, 2), (57, 3), (300, 4),
+                                    (2000, 5), (20000, 6)])
+def test_random_tree_dp(orc, n, seed):
+    g = gg.relabel(gg.random_tree(n, seed), seed)
+    check_mvc(orc, g, pins.tree_mvc(g))
+
+
+def test_forest_dp(orc):
+    g = gg.relabel(gg.disjoint_union([gg.random_tree(n, s) for n, s in
+                                      [(1, 1), (2, 2), (9, 3), (40, 4), (333, 5)]]), 9)
+    check_mvc(orc, g, pins.tree_mvc(g))
+
+
+# -------------------------------------------------------------- invariances
+
+def test_relabel_invariance(orc):
+    for seed in range(1, 9):
+        g = gg.config1_gnp60(seed)
+        base = orc.mvc(g)["size"]
+        for s2 in range(3):
+            h = gg.relabel(g, 77 + s2)
+            assert orc.mvc(h)["size"] == base
+
+
+# ------------------------------------------------------ the larger workloads
+
+def test_blocks_hubs_bounds(orc):
+    """Component-splitting workload: MVC lies between the sum of the blocks'
+    MVCs (a cover restricted to a block covers it) and that sum plus the 8
+    hubs (hubs in, then each block separately); the block values come from
+    the independent bitset MIS search."""
+    g = gg.config2_blocks_hubs(nblocks=4, bsize=40, nhubs=3, per_block=12)
+    r = orc.mvc(g)
+    assert_cover(g, r["cover"], size=r["size"])
+    deg = np.diff(g.offsets.astype(np.int64))
+    hubs = np.flatnonzero(deg >= 4 * 12)
+    assert hubs.size == 3
+    keep = np.ones(g.n, bool)
+    keep[hubs] = False
+    u, v = g.edges()
+    m = keep[u] & keep[v]
+    rest = gg.from_edges(g.n, u[m], v[m])
+    lo = rest.n - pins.mis_bitset(rest)
+    assert lo <= r["size"] <= lo + 3
+    # exact value by the decomposition over which hubs stay out of the cover
+    adj = [set() for _ in range(g.n)]
+    for a, b in zip(u.tolist(), v.tolist()):
+        adj[a].add(b)
+        adj[b].add(a)
+    best = None
+    for mask in range(1 << hubs.size):
+        out = [int(hubs[i]) for i in range(hubs.size) if mask >> i & 1]
+        forced = set().union(*[adj[h] for h in out]) if out else set()
+        keep2 = keep.copy()
+        keep2[list(forced)] = False
+        m2 = keep2[u] & keep2[v]
+        sub = gg.from_edges(g.n, u[m2], v[m2])
+        val = (hubs.size - len(out)) + len(forced) + sub.n - pins.mis_bitset(sub)
+        best = val if best is None else min(best, val)
+    assert r["size"] == best
+
+
+def test_planted_power_law_pvc(orc):
+    """Large sparse PVC workload shape (scaled to 200k vertices): the planted
+    set bounds MVC from above, and PVC flips exactly at the oracle's MVC."""
+    g = gg.chung_lu_planted(200_000, 1_000_000, 2.1, 12_000, seed=3)
+    r = orc.mvc(g)
+    assert r["size"] <= g.planted.size
+    assert_cover(g, r["cover"], size=r["size"])
+    assert not orc.pvc(g, r["size"] - 1)["yes"]
+    y = orc.pvc(g, r["size"])
+    assert y["yes"]
+    assert_cover(g, y["cover"], at_most=r["size"])
+
+
+def _maximal_matching_size(u, v, alive):
+    used = ~alive.copy()
+    size = 0
+    for a, b in zip(u.tolist(), v.tolist()):
+        if not used[a] and not used[b]:
+            used[a] = used[b] = True
+            size += 1
+    return size
+
+
+def test_blocks_hubs_full_size_decomposition(orc):
+    """The 1,928-vertex component-splitting workload, pinned exactly.
+
+    Hubs are pairwise non-adjacent, so for the set X of hubs left out of a
+    cover, all of N(X) is in it and the rest is a cover of the blocks minus
+    N(X):  MVC = min_X [|H| - |X| + |N(X)| + MVC(G - H - N(X))].
+    The block term comes from the independent MIS search; a subset X is
+    skipped when |H| - |X| + |N(X)| + (a maximal matching of what is left),
+    a lower bound, already reaches the best value found.
+    """
+    g = gg.config2_blocks_hubs()
+    r = orc.mvc(g)
+    assert_cover(g, r["cover"], size=r["size"])
+    deg = np.diff(g.offsets.astype(np.int64))
+    hubs = np.flatnonzero(deg >= 600)
+    assert hubs.size == 8
+    u, v = g.edges()
+    nonhub = np.ones(g.n, bool)
+    nonhub[hubs] = False
+    nbr = []
+    for h in hubs:
+        nbr.append(g.cols[g.offsets[h]:g.offsets[h + 1]].astype(np.int64))
+    best = None
+    order = sorted(range(1 << hubs.size), key=lambda m: bin(m).count("1"))
+    for mask in order:
+        out = [i for i in range(hubs.size) if mask >> i & 1]
+        alive = nonhub.copy()
+        for i in out:
+            alive[nbr[i]] = False
+        forced = int(nonhub.sum() - alive.sum())
+        base = hubs.size - len(out) + forced
+        m = alive[u] & alive[v]
+        if best is not None:
+            if base + _maximal_matching_size(u[m], v[m], alive) >= best:
+                continue
+        sub = gg.from_edges(g.n, u[m], v[m])
+        val = base + sub.n - pins.mis_bitset(sub)
+        best = val if best is None else min(best, val)
+    assert r["size"] == best
