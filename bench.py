@@ -1,0 +1,152 @@
+#!/usr/bin/env python3
+"""Benchmark: exact MVC of the component-splitting blocks-and-hubs graph on
+one MI355X (time-to-solution and search-nodes/s), with the HBM-roofline view
+of the persistent search kernel and the CPU oracle timed beside it.
+
+Workload (seeded, synthetic): 20 uniform random 3-regular blocks of 96
+vertices plus 8 hubs, each joined to 30 random vertices of every block;
+n = 1,928, m = 7,680, CSR uint32 offsets / uint32 cols, resident in HBM
+before the timed region.  One step = one vc_min call on it (validation,
+degrees, greedy bound, root reduction, induce, search, cover assembly and
+the cover copied back to the host).
+
+Prints one JSON line.  Only one GPU is supported: --gpus N with N > 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MVC time-to-solution & search-nodes/s; batched graphs/s; "
+          "p50/p99 solve latency")
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_blocks_hubs_traffic.json")
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("search.hip", "dev_common.hpp", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2512_18334_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(per_launch_alg_bytes: float):
+    """HBM bytes per search launch from the committed rocprofv3 counters, or
+    None if they are missing or were taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_source_sha():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(g, budget_s: float):
+    import oracle
+    reps, t0, nodes = 0, time.perf_counter(), 0
+    while True:
+        r = oracle.mvc(g)
+        nodes += r["nodes"]
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": nodes / el, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full sequential solves of the same graph "
+                      f"({el:.1f} s; MVC {r['size']}, {r['nodes']} tree nodes each, "
+                      f"{el / reps * 1e3:.1f} ms per solve)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the search shards across GPUs only by instance, see the design notes",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_18334_amd import graphgen as gg
+    from paper_2512_18334_amd import vc
+
+    if not os.path.exists(vc.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+
+    g = gg.config2_blocks_hubs()
+    dg = vc.DeviceGraph.from_graph(g, "cuda:0")
+    torch.cuda.synchronize()
+    solver = vc.Solver(0)
+    for _ in range(args.warmup):
+        solver.mvc(dg)
+    torch.cuda.synchronize()
+
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = solver.mvc(dg)
+        stats.append(r.stats)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    size = r.size
+
+    nodes = sum(s["tree_nodes"] for s in stats)
+    ms_step = el * 1e3 / args.steps
+    search_ms = sum(s["ms_search"] for s in stats) / len(stats)
+    # algorithmic HBM bytes of one search launch: every pushed node slot is
+    # written once and read once, the root slot is read once, and each
+    # registered component writes one registry entry and one cover bitmap
+    s0 = stats[-1]
+    alg_bytes = sum((2 * s["pushes"] + 1) * s["slot_bytes"]
+                    + (s["components"] + s["component_branches"])
+                    * (32 + s["bitmap_bytes"]) for s in stats) / len(stats)
+    achieved = alg_bytes / (search_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": nodes / el,
+        "unit": "search-nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": "mvc_blocks_hubs_n1928", "graph": g.name, "n": g.n,
+                   "m": g.m, "mvc": size, "time_to_solution_ms": ms_step,
+                   "tree_nodes_per_solve": nodes / args.steps,
+                   "search_kernel_ms": search_ms, "workers": s0["workers"],
+                   "deg_bytes": s0["deg_bytes"],
+                   "component_branches_per_solve":
+                       sum(s["component_branches"] for s in stats) / len(stats)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(alg_bytes)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * vc.h -- C ABI of libvc: exact minimum / parameterized vertex cover on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. II-A of "Faster Vertex Cover Algorithms on GPUs with
+ * Component-Aware Parallel Branching"): for a simple undirected graph G,
+ *   MVC(G)    = the smallest |C| such that every edge has an endpoint in C;
+ *   PVC(G, k) = whether some vertex cover has |C| <= k.
+ * Method: component-aware branch-and-reduce (Alg. 2) with the degree-one,
+ * degree-two triangle and high-degree rules (Sec. II-B), clique / chordless
+ * cycle component rules (Sec. III-D), a component branch registry whose
+ * post-processing runs in the last descendant to finish (Sec. III-C),
+ * early termination for PVC (Sec. III-E), and the root reduce-then-induce
+ * step with narrow degree types (Sec. IV-B, IV-D).  Every step runs in HIP
+ * kernels on the device; the host only validates, plans and launches.
+ *
+ * Conventions for every entry point:
+ *   - Return value: VC_OK (0) or a negative vc_status.  On error no output
+ *     is written.
+ *   - Graphs are borrowed for the duration of the call and never modified.
+ *   - Output arrays are owned by the caller and live in host memory.
+ *   - A vc_ctx owns all device memory it allocates; it is not thread-safe
+ *     (one host thread at a time per context).
+ */
+#ifndef VC_H
+#define VC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VC_OK = 0,
+    VC_EINVAL = -1,      /* malformed graph or argument                      */
+    VC_ENOMEM = -2,      /* device memory (or a capacity limit) exhausted    */
+    VC_EDEVICE = -3,     /* a HIP call failed                                */
+    VC_EAGAIN = -4,      /* a submitted request is still pending              */
+    VC_ETIMEDOUT = -5,   /* the search-node limit in vc_opts was reached     */
+    VC_ECANCELED = -6,   /* the request was cancelled                        */
+    VC_ERANGE = -7       /* a size does not fit the library's limits         */
+} vc_status;
+
+/* vc_csr.flags */
+#define VC_CSR_DEVICE 1u /* offsets and cols are device pointers (HBM)      */
+
+/*
+ * A simple undirected graph in symmetric CSR (Sec. II-A, IV-A):
+ *   offsets[n+1] (uint32, offsets[0] = 0, non-decreasing, offsets[n] = nnz)
+ *   cols[nnz]    (uint16 when col_bytes == 2, which needs n <= 65536, else
+ *                 uint32), both directions of every edge present.
+ * Rows need not be sorted.  Self-loops, repeated entries in a row, asymmetric
+ * rows and cols >= n are rejected with VC_EINVAL.  nnz must be < 2^32.
+ * With VC_CSR_DEVICE both arrays live in device memory of the context's
+ * device; otherwise they are host memory.
+ */
+typedef struct {
+    uint32_t n;
+    uint64_t nnz;
+    const uint32_t *offsets;
+    const void *cols;
+    uint32_t col_bytes;
+    uint32_t flags;
+} vc_csr;
+
+/* vc_opts.flags: ablation switches (all off by default) */
+#define VC_OPT_NO_COMPONENTS 1u /* never branch on components (Alg. 1)     */
+#define VC_OPT_NO_LOAD_BALANCE 2u /* no worklist donation: every child stays
+                                     on its worker's own stack              */
+#define VC_OPT_VALIDATE_SKIP 4u /* trust the caller: skip the CSR checks     */
+
+/*
+ * Tuning knobs.  Zero in any field selects the library default.
+ *   workers       persistent search workers (one 64-lane wave each); the
+ *                 default fills every compute unit within the LDS and HBM
+ *                 budgets.
+ *   donate_slack  a worker donates a child to the shared worklist while
+ *                 idle workers outnumber queued nodes by more than this.
+ *   worklist_cap  worklist capacity in nodes.
+ *   registry_cap  component branch registry capacity in entries; when full,
+ *                 the search branches on a vertex instead (still exact).
+ *   hbm_budget    bytes of device memory the search may use.
+ *   node_limit    stop with VC_ETIMEDOUT after this many tree nodes.
+ *   watchdog_ms   a worker that has waited this long for work while work
+ *                 is still outstanding stops the search with VC_EDEVICE
+ *                 (default 120000).
+ */
+typedef struct {
+    uint32_t workers;
+    uint32_t donate_slack;
+    uint32_t worklist_cap;
+    uint32_t registry_cap;
+    uint64_t hbm_budget;
+    uint64_t node_limit;
+    uint32_t flags;
+    uint32_t watchdog_ms;
+} vc_opts;
+
+/* Statistics of the last completed solve on a context. */
+typedef struct {
+    uint64_t tree_nodes;         /* search-tree nodes processed (Table III) */
+    uint64_t component_branches; /* nodes that branched on components      */
+    uint64_t components;         /* component children registered          */
+    uint64_t donations;          /* nodes handed to the shared worklist    */
+    uint64_t pushes;             /* node slots written to HBM (stacks and
+                                    worklist); each is read back once       */
+    uint32_t n_input;            /* vertices of the input graph             */
+    uint32_t n_kernel;           /* vertices left after the root reduction  */
+    uint64_t nnz_kernel;         /* CSR entries of the induced subgraph     */
+    uint32_t forced_root;        /* vertices the root reduction put in C   */
+    uint32_t greedy_size;        /* initial bound from the greedy cover     */
+    uint32_t max_degree_kernel;  /* maximum degree of the induced subgraph  */
+    uint32_t deg_bytes;          /* 1, 2 or 4: degree-array element size    */
+    uint32_t workers;            /* search workers launched                 */
+    uint32_t root_rounds;        /* rounds of the root reduction            */
+    uint32_t slot_bytes;         /* bytes of one search-node slot           */
+    uint32_t bitmap_bytes;       /* bytes of one registry cover bitmap      */
+    double ms_root;              /* device time: degrees, greedy, reduce    */
+    double ms_induce;            /* device time: induce + plan readback     */
+    double ms_search;            /* device time: persistent search          */
+    double ms_total;             /* wall time of the whole call             */
+} vc_stats;
+
+typedef struct vc_ctx vc_ctx;
+
+/*
+ * Create a context on HIP device `device`.  `stream` is a hipStream_t to run
+ * on (NULL: the library creates its own non-blocking stream); the caller
+ * keeps ownership of a stream it passes.  `opts` may be NULL.
+ */
+vc_status vc_ctx_create(int device, void *stream, const vc_opts *opts,
+                        vc_ctx **out);
+
+/* Release every device buffer of the context; ctx may be NULL. */
+vc_status vc_ctx_destroy(vc_ctx *ctx);
+
+/*
+ * Check a CSR graph against the rules stated at vc_csr.  Host arrays are
+ * checked exactly on the host and ctx may be NULL; device arrays need a
+ * context and are checked by kernels (offsets, ranges, self-loops, repeated
+ * entries in sorted rows or unsorted rows of up to 512 entries, symmetry by
+ * a 64-bit hash of the unordered pairs).  Returns VC_OK or VC_EINVAL
+ * (VC_ERANGE when nnz >= 2^32).
+ */
+vc_status vc_validate(vc_ctx *ctx, const vc_csr *g);
+
+/*
+ * Minimum vertex cover (Alg. 2).  Writes MVC(G) to *size and, if cover is
+ * not NULL, one minimum cover (original vertex ids, ascending, capacity n)
+ * to cover with its length (== *size) to *cover_len.
+ */
+vc_status vc_min(vc_ctx *ctx, const vc_csr *g, uint32_t *size,
+                 uint32_t *cover, uint32_t *cover_len);
+
+/*
+ * Parameterized vertex cover (Sec. II-B, III-E): *yes = 1 iff MVC(G) <= k.
+ * On yes and a non-NULL cover, writes a cover of size <= k (ascending ids)
+ * and its length; on no, *cover_len = 0.  The search stops as soon as a
+ * cover within k is known.
+ */
+vc_status vc_param(vc_ctx *ctx, const vc_csr *g, uint32_t k, int *yes,
+                   uint32_t *cover, uint32_t *cover_len);
+
+/* Copy the statistics of the last completed solve. */
+vc_status vc_last_stats(vc_ctx *ctx, vc_stats *out);
+
+/* Human-readable name of a status code (static storage). */
+const char *vc_status_str(vc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VC_H */

@@ -1,0 +1,563 @@
+// api.hip -- host runtime of libvc: the C ABI declared in include/vc.h.
+//
+// A solve runs, all on the context's stream:
+//   validate -> degrees -> greedy bound -> root reduction -> induce ->
+//   plan (one small readback) -> persistent search -> cover assembly.
+// The host only checks arguments, sizes buffers and launches; every step of
+// the method runs in the kernels of root.hip and search.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+#include "root.hpp"
+#include "vc.h"
+
+using namespace vc;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+    if (bytes <= b.cap && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e) return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes < 256 ? 256 : bytes;
+    want = (want + 4095) & ~(size_t)4095;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e) return e;
+    b.cap = want;
+    return hipSuccess;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct vc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    vc_opts opts{};
+    vc_stats last{};
+    int cus = 0;
+    size_t lds_max = 0;
+    int wall_khz = 100000;  // wall_clock64() rate
+    // input copies (host CSR) and root buffers
+    DevBuf in_off, in_col;
+    DevBuf rdeg, gdeg, gin, addf, newly, flags, newid, oldid, kdeg, koff, kcol, cover, scan_tmp,
+        ctr, hsum;
+    // search buffers
+    DevBuf stacks, wl_slots, wl_seq, ctl, reg, bitmaps;
+    hipEvent_t ev[6] = {};
+};
+
+namespace {
+
+vc_status hip_status(hipError_t e) {
+    if (e == hipErrorOutOfMemory) return VC_ENOMEM;
+    return VC_EDEVICE;
+}
+
+#define HIPCHK(x)                                                                 \
+    do {                                                                          \
+        hipError_t _e = (x);                                                      \
+        if (_e != hipSuccess) {                                                   \
+            if (getenv("VC_DEBUG"))                                               \
+                fprintf(stderr, "libvc: %s failed: %s\n", #x, hipGetErrorString(_e)); \
+            return hip_status(_e);                                                \
+        }                                                                         \
+    } while (0)
+
+// Exact host-side check of a host CSR against the rules stated in vc.h.
+vc_status validate_host(const vc_csr* g) {
+    const uint32_t n = g->n;
+    const uint32_t* off = g->offsets;
+    if (off[0] != 0 || (uint64_t)off[n] != g->nnz) return VC_EINVAL;
+    for (uint32_t v = 0; v < n; ++v)
+        if (off[v] > off[v + 1]) return VC_EINVAL;
+    std::vector<uint32_t> col(g->nnz);
+    for (uint64_t e = 0; e < g->nnz; ++e)
+        col[e] = g->col_bytes == 2 ? ((const uint16_t*)g->cols)[e] : ((const uint32_t*)g->cols)[e];
+    for (uint32_t v = 0; v < n; ++v) {
+        auto b = col.begin() + off[v], en = col.begin() + off[v + 1];
+        std::sort(b, en);
+        for (auto it = b; it != en; ++it) {
+            if (*it >= n || *it == v) return VC_EINVAL;
+            if (it != b && *(it - 1) == *it) return VC_EINVAL;
+        }
+    }
+    for (uint32_t v = 0; v < n; ++v)
+        for (uint32_t e = off[v]; e < off[v + 1]; ++e) {
+            const uint32_t w = col[e];
+            if (!std::binary_search(col.begin() + off[w], col.begin() + off[w + 1], v))
+                return VC_EINVAL;
+        }
+    return VC_OK;
+}
+
+vc_status check_args(const vc_csr* g) {
+    if (!g) return VC_EINVAL;
+    if (g->col_bytes != 2 && g->col_bytes != 4) return VC_EINVAL;
+    if (g->col_bytes == 2 && g->n > 65536u) return VC_EINVAL;
+    if (g->nnz >= (1ull << 32)) return VC_ERANGE;
+    if (g->n >= 0x7FFFFFFFu) return VC_ERANGE;
+    if (!g->offsets) return VC_EINVAL;
+    if (g->nnz && !g->cols) return VC_EINVAL;
+    return VC_OK;
+}
+
+vc_status device_validate(vc_ctx* c, const RootGraph& rg) {
+    HIPCHK(ensure(c->ctr, CTR_COUNT * 4));
+    HIPCHK(ensure(c->hsum, 8));
+    HIPCHK(hipMemsetAsync(c->ctr.p, 0, CTR_COUNT * 4, c->stream));
+    HIPCHK(hipMemsetAsync(c->hsum.p, 0, 8, c->stream));
+    uint32_t bad = 0;
+    HIPCHK(root_validate(rg, (uint32_t*)c->ctr.p, (unsigned long long*)c->hsum.p, c->stream, &bad));
+    return bad ? VC_EINVAL : VC_OK;
+}
+
+// Place the graph on the device (uploading a host CSR) and validate it.
+vc_status stage_graph(vc_ctx* c, const vc_csr* g, RootGraph* rg) {
+    vc_status st = check_args(g);
+    if (st) return st;
+    const bool skip = (c->opts.flags & VC_OPT_VALIDATE_SKIP) != 0;
+    rg->n = g->n;
+    rg->nnz = g->nnz;
+    rg->col_bytes = g->col_bytes;
+    if (g->flags & VC_CSR_DEVICE) {
+        rg->off = g->offsets;
+        rg->col = g->cols;
+        if (!skip && g->n) {
+            st = device_validate(c, *rg);
+            if (st) return st;
+        }
+        return VC_OK;
+    }
+    if (!skip) {
+        st = validate_host(g);
+        if (st) return st;
+    }
+    HIPCHK(ensure(c->in_off, 4ull * (g->n + 1)));
+    HIPCHK(ensure(c->in_col, (size_t)g->col_bytes * (g->nnz ? g->nnz : 1)));
+    HIPCHK(hipMemcpyAsync(c->in_off.p, g->offsets, 4ull * (g->n + 1), hipMemcpyHostToDevice,
+                          c->stream));
+    if (g->nnz)
+        HIPCHK(hipMemcpyAsync(c->in_col.p, g->cols, (size_t)g->col_bytes * g->nnz,
+                              hipMemcpyHostToDevice, c->stream));
+    rg->off = (const uint32_t*)c->in_off.p;
+    rg->col = c->in_col.p;
+    return VC_OK;
+}
+
+vc_status root_buffers(vc_ctx* c, const RootGraph& g, RootBufs* b) {
+    const size_t n = g.n, n1 = g.n + 1;
+    HIPCHK(ensure(c->rdeg, 4 * n1));
+    HIPCHK(ensure(c->gdeg, 4 * n1));
+    HIPCHK(ensure(c->gin, n1));
+    HIPCHK(ensure(c->addf, n1));
+    HIPCHK(ensure(c->newly, n1));
+    HIPCHK(ensure(c->flags, 4 * (n1 + 1)));
+    HIPCHK(ensure(c->newid, 4 * (n1 + 1)));
+    HIPCHK(ensure(c->oldid, 4 * n1));
+    HIPCHK(ensure(c->kdeg, 4 * (n1 + 1)));
+    HIPCHK(ensure(c->koff, 4 * (n1 + 1)));
+    HIPCHK(ensure(c->kcol, 4 * (g.nnz ? g.nnz : 1)));
+    HIPCHK(ensure(c->cover, 4 * n1));
+    HIPCHK(ensure(c->scan_tmp, 4 * (n / 2048 + 4)));
+    HIPCHK(ensure(c->ctr, CTR_COUNT * 4));
+    HIPCHK(ensure(c->hsum, 8));
+    b->rdeg = (uint32_t*)c->rdeg.p;
+    b->gdeg = (uint32_t*)c->gdeg.p;
+    b->gin = (uint8_t*)c->gin.p;
+    b->addf = (uint8_t*)c->addf.p;
+    b->newly = (uint8_t*)c->newly.p;
+    b->flags = (uint32_t*)c->flags.p;
+    b->newid = (uint32_t*)c->newid.p;
+    b->oldid = (uint32_t*)c->oldid.p;
+    b->kdeg = (uint32_t*)c->kdeg.p;
+    b->koff = (uint32_t*)c->koff.p;
+    b->kcol = c->kcol.p;
+    b->cover = (uint32_t*)c->cover.p;
+    b->scan_tmp = (uint32_t*)c->scan_tmp.p;
+    b->ctr = (uint32_t*)c->ctr.p;
+    b->hsum = (unsigned long long*)c->hsum.p;
+    return VC_OK;
+}
+
+// Copy `count` cover ids from the device list into the caller's array.
+vc_status fetch_cover(vc_ctx* c, const RootBufs& b, uint32_t count, uint32_t* cover,
+                      uint32_t* cover_len) {
+    if (cover && count)
+        HIPCHK(hipMemcpyAsync(cover, b.cover, 4ull * count, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (cover_len) *cover_len = count;
+    return VC_OK;
+}
+
+struct Outcome {
+    uint32_t size = 0;  // MVC size, or the size of the cover found (PVC)
+    int yes = 0;
+    uint32_t cover_count = 0;
+};
+
+// The whole pipeline.  pvc: 0 = MVC, 1 = PVC with bound k.
+vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, uint32_t* cover,
+                uint32_t* cover_len) {
+    const double t0 = now_ms();
+    vc_stats stv{};
+    RootGraph rg;
+    vc_status st = stage_graph(c, g, &rg);
+    if (st) return st;
+    stv.n_input = g->n;
+    if (g->n == 0 || g->nnz == 0) {
+        out->size = 0;
+        out->yes = 1;
+        out->cover_count = 0;
+        if (cover_len) *cover_len = 0;
+        stv.ms_total = now_ms() - t0;
+        c->last = stv;
+        return VC_OK;
+    }
+    RootBufs b;
+    st = root_buffers(c, rg, &b);
+    if (st) return st;
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemsetAsync(b.ctr, 0, CTR_COUNT * 4, s));
+    HIPCHK(hipEventRecord(c->ev[0], s));
+    HIPCHK(root_init(rg, b, s));
+    uint32_t grounds = 0;
+    HIPCHK(root_greedy(rg, b, s, &grounds));
+    uint32_t gsize = 0;
+    HIPCHK(hipMemcpyAsync(&gsize, b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    stv.greedy_size = gsize;
+
+    auto finish_with_greedy = [&](int yes) -> vc_status {
+        // the greedy cover is the answer (MVC), or a PVC yes within k
+        HIPCHK(root_cover(rg, b, 0, 0, nullptr, s));
+        uint32_t cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (cnt != gsize) return VC_EDEVICE;
+        out->size = gsize;
+        out->yes = yes;
+        out->cover_count = cnt;
+        vc_status r = fetch_cover(c, b, cnt, cover, cover_len);
+        stv.ms_total = now_ms() - t0;
+        c->last = stv;
+        return r;
+    };
+    auto finish_no = [&]() -> vc_status {
+        out->yes = 0;
+        out->size = 0;
+        out->cover_count = 0;
+        if (cover_len) *cover_len = 0;
+        stv.ms_total = now_ms() - t0;
+        c->last = stv;
+        return VC_OK;
+    };
+
+    int best0;
+    if (pvc) {
+        if (gsize <= k) return finish_with_greedy(1);
+        best0 = (int)k + 1;
+    } else {
+        best0 = (int)gsize;
+    }
+
+    // root reduction to a fixpoint under the bound best0 (Sec. IV-B)
+    uint32_t rounds = 0;
+    HIPCHK(root_reduce(rg, b, best0, s, 1u << 16, &rounds));
+    stv.root_rounds = rounds;
+    uint32_t sroot = 0;
+    HIPCHK(hipMemcpyAsync(&sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(c->ev[1], s));
+    HIPCHK(hipStreamSynchronize(s));
+    stv.forced_root = sroot;
+    if ((int)sroot >= best0) {
+        // no cover below best0 exists
+        return pvc ? finish_no() : finish_with_greedy(1);
+    }
+
+    // induce the subgraph on the vertices that still have edges
+    HIPCHK(root_induce_a(rg, b, s));
+    uint32_t hdr[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&hdr[0], b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const uint32_t np = hdr[0], dmax = hdr[1];
+    stv.n_kernel = np;
+    stv.max_degree_kernel = dmax;
+    const int kbest0 = best0 - (int)sroot;
+    int kbest = kbest0;
+    bool improved = false;
+    uint64_t nnzp = 0;
+    uint32_t* root_bitmap = nullptr;
+    if (np == 0) {
+        // the rules covered every edge: |S_root| < best0 is attained
+        kbest = 0;
+        improved = true;
+    } else {
+        const uint32_t kcol_bytes = np <= 65536u ? 2u : 4u;
+        HIPCHK(root_induce_b(rg, b, np, kcol_bytes, s));
+        uint32_t nz = 0;
+        HIPCHK(hipMemcpyAsync(&nz, b.koff + np, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(c->ev[2], s));
+        HIPCHK(hipStreamSynchronize(s));
+        nnzp = nz;
+        stv.nnz_kernel = nnzp;
+
+        // ------------------------------------------------ plan
+        const uint32_t deg_bytes = dmax <= 254u ? 1u : (dmax <= 65534u ? 2u : 4u);
+        stv.deg_bytes = deg_bytes;
+        const uint32_t n_pad = (np + 63u) & ~63u;
+        const LdsPlan lp = lds_plan(n_pad, deg_bytes);
+        if (lp.bytes > c->lds_max) return VC_ERANGE;
+        int bpc = 0;
+        HIPCHK(search_occupancy(deg_bytes, kcol_bytes, lp.bytes, &bpc));
+        if (bpc < 1) return VC_ERANGE;
+        uint32_t workers = c->opts.workers ? c->opts.workers : (uint32_t)(bpc * c->cus);
+        const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes;
+        uint32_t depth = std::min<uint32_t>(np, (uint32_t)kbest0) + np / 4u + 16u;
+        const uint64_t budget = c->opts.hbm_budget ? c->opts.hbm_budget : (48ull << 30);
+        const uint64_t per_worker = (uint64_t)depth * slot_bytes;
+        uint64_t wmax = (budget / 2) / (per_worker ? per_worker : 1);
+        if (wmax < 1) wmax = 1;
+        if (workers > wmax) workers = (uint32_t)wmax;
+        if (workers < 1) workers = 1;
+        const uint32_t wl_cap = c->opts.worklist_cap ? c->opts.worklist_cap
+                                                     : std::max<uint32_t>(1024u, 4u * workers);
+        const uint32_t bm_words = ((np + 31u) / 32u + 31u) & ~31u;  // whole 128-byte lines
+        uint64_t reg_cap = c->opts.registry_cap ? c->opts.registry_cap : (1u << 20);
+        const uint64_t reg_bytes_each = sizeof(RegEntry) + 4ull * bm_words;
+        const uint64_t reg_budget = budget / 4;
+        if (reg_cap * reg_bytes_each > reg_budget) reg_cap = reg_budget / reg_bytes_each;
+        if (reg_cap < 64) reg_cap = 64;
+        stv.workers = workers;
+
+        HIPCHK(ensure(c->stacks, (size_t)workers * depth * slot_bytes));
+        HIPCHK(ensure(c->wl_slots, (size_t)wl_cap * slot_bytes));
+        HIPCHK(ensure(c->wl_seq, 8ull * wl_cap));
+        HIPCHK(ensure(c->ctl, sizeof(Ctl)));
+        HIPCHK(ensure(c->reg, sizeof(RegEntry) * reg_cap));
+        HIPCHK(ensure(c->bitmaps, 4ull * bm_words * reg_cap));
+
+        SearchArgs a{};
+        a.n = np;
+        a.n_pad = n_pad;
+        a.off = b.koff;
+        a.col = b.kcol;
+        a.slot_bytes = slot_bytes;
+        a.stack_depth = depth;
+        a.stacks = (uint8_t*)c->stacks.p;
+        a.wl_slots = (uint8_t*)c->wl_slots.p;
+        a.wl_seq = (uint64_t*)c->wl_seq.p;
+        a.wl_cap = wl_cap;
+        a.reg_cap = (uint32_t)reg_cap;
+        a.ctl = (Ctl*)c->ctl.p;
+        a.reg = (RegEntry*)c->reg.p;
+        a.bitmaps = (uint32_t*)c->bitmaps.p;
+        a.bm_words = bm_words;
+        a.lds_L = lp.L;
+        a.lds_Q = lp.Q;
+        a.lds_R = lp.R;
+        a.lds_VB = lp.VB;
+        a.lds_PB = lp.PB;
+        a.lds_misc = lp.misc;
+        a.lds_bytes = lp.bytes;
+        a.pvc = pvc;
+        a.k = pvc ? (int)k - (int)sroot : 0;
+        a.flags = c->opts.flags;
+        a.donate_slack = c->opts.donate_slack;
+        a.node_limit = c->opts.node_limit;
+        a.watchdog_ticks = (uint64_t)c->wall_khz * (c->opts.watchdog_ms ? c->opts.watchdog_ms : 120000u);
+
+        HIPCHK(launch_search_init(a, kbest0, deg_bytes, b.kdeg, s));
+        HIPCHK(hipEventRecord(c->ev[3], s));
+        HIPCHK(launch_search(a, deg_bytes, kcol_bytes, workers, s));
+        HIPCHK(hipEventRecord(c->ev[4], s));
+        Ctl ctl;
+        RegEntry root;
+        HIPCHK(hipMemcpyAsync(&ctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&root, c->reg.p, sizeof(RegEntry), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        stv.tree_nodes = ctl.nodes;
+        stv.component_branches = ctl.comp_branches;
+        stv.components = ctl.components;
+        stv.donations = ctl.donations;
+        stv.pushes = ctl.pushes;
+        stv.slot_bytes = slot_bytes;
+        stv.bitmap_bytes = 4u * bm_words;
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[3], c->ev[4]));
+        stv.ms_search = ms;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+        stv.ms_induce = ms;
+        if (ctl.err) {
+            c->last = stv;
+            return (vc_status)ctl.err;
+        }
+        if (root.best < kbest0) {
+            if (root.cover_size != root.best) return VC_EDEVICE;  // internal invariant
+            improved = true;
+            kbest = root.best;
+            root_bitmap = (uint32_t*)c->bitmaps.p;
+        }
+    }
+    {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        stv.ms_root = ms;
+    }
+    if (!improved) return pvc ? finish_no() : finish_with_greedy(1);
+
+    const uint32_t size = sroot + (uint32_t)kbest;
+    HIPCHK(root_cover(rg, b, np, 1, root_bitmap, s));
+    uint32_t cnt = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (cnt != size) return VC_EDEVICE;  // internal invariant: |cover| == size
+    out->size = size;
+    out->yes = pvc ? (size <= k) : 1;
+    out->cover_count = cnt;
+    st = fetch_cover(c, b, cnt, cover, cover_len);
+    stv.ms_total = now_ms() - t0;
+    c->last = stv;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+vc_status vc_ctx_create(int device, void* stream, const vc_opts* opts, vc_ctx** out) {
+    if (!out) return VC_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return VC_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return VC_EDEVICE;
+    vc_ctx* c = new (std::nothrow) vc_ctx();
+    if (!c) return VC_ENOMEM;
+    c->device = device;
+    if (opts) c->opts = *opts;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return VC_EDEVICE;
+    }
+    c->cus = prop.multiProcessorCount;
+    c->lds_max = prop.sharedMemPerBlock;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess &&
+        khz > 0)
+        c->wall_khz = khz;
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return VC_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    for (auto& e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            vc_ctx_destroy(c);
+            return VC_EDEVICE;
+        }
+    }
+    *out = c;
+    return VC_OK;
+}
+
+vc_status vc_ctx_destroy(vc_ctx* c) {
+    if (!c) return VC_OK;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    DevBuf* bufs[] = {&c->in_off, &c->in_col, &c->rdeg, &c->gdeg, &c->gin, &c->addf,
+                      &c->newly, &c->flags, &c->newid, &c->oldid, &c->kdeg, &c->koff,
+                      &c->kcol, &c->cover, &c->scan_tmp, &c->ctr, &c->hsum, &c->stacks,
+                      &c->wl_slots, &c->wl_seq, &c->ctl, &c->reg, &c->bitmaps};
+    for (DevBuf* b : bufs)
+        if (b->p) hipFree(b->p);
+    for (auto& e : c->ev)
+        if (e) hipEventDestroy(e);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    delete c;
+    return VC_OK;
+}
+
+vc_status vc_validate(vc_ctx* c, const vc_csr* g) {
+    vc_status st = check_args(g);
+    if (st) return st;
+    if (!(g->flags & VC_CSR_DEVICE)) return validate_host(g);
+    if (!c) return VC_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    if (g->n == 0) return g->nnz == 0 ? VC_OK : VC_EINVAL;
+    RootGraph rg{g->n, g->nnz, g->offsets, g->cols, g->col_bytes};
+    return device_validate(c, rg);
+}
+
+vc_status vc_min(vc_ctx* c, const vc_csr* g, uint32_t* size, uint32_t* cover,
+                 uint32_t* cover_len) {
+    if (!c || !size) return VC_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    Outcome o;
+    vc_status st = solve(c, g, 0, 0, &o, cover, cover_len);
+    if (st) return st;
+    *size = o.size;
+    return VC_OK;
+}
+
+vc_status vc_param(vc_ctx* c, const vc_csr* g, uint32_t k, int* yes, uint32_t* cover,
+                   uint32_t* cover_len) {
+    if (!c || !yes) return VC_EINVAL;
+    if (k > 0x3FFFFFF0u) k = 0x3FFFFFF0u;
+    if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    Outcome o;
+    vc_status st = solve(c, g, 1, k, &o, cover, cover_len);
+    if (st) return st;
+    *yes = o.yes;
+    if (!o.yes && cover_len) *cover_len = 0;
+    return VC_OK;
+}
+
+vc_status vc_last_stats(vc_ctx* c, vc_stats* out) {
+    if (!c || !out) return VC_EINVAL;
+    *out = c->last;
+    return VC_OK;
+}
+
+const char* vc_status_str(vc_status s) {
+    switch (s) {
+        case VC_OK: return "ok";
+        case VC_EINVAL: return "invalid argument or graph";
+        case VC_ENOMEM: return "out of device memory or capacity";
+        case VC_EDEVICE: return "device error";
+        case VC_EAGAIN: return "pending";
+        case VC_ETIMEDOUT: return "node limit reached";
+        case VC_ECANCELED: return "cancelled";
+        case VC_ERANGE: return "size beyond the library's limits";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// dev_common.hpp -- wave64 primitives and scoped atomics shared by the
+// libvc kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define VC_WAVE 64
+
+namespace vc {
+
+// ----------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ uint32_t lane() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t popc(uint64_t m) { return __popcll(m); }
+
+__device__ __forceinline__ uint32_t shfl(uint32_t x, uint32_t src) {
+    return (uint32_t)__shfl((int)x, (int)src, 64);
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t y = __shfl_xor(x, o, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t y = (uint32_t)__shfl_xor((int)x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t y = (uint32_t)__shfl_xor((int)x, o, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// inclusive prefix sum across the 64 lanes
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t l = lane();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
+        if (l >= (uint32_t)o) x += y;
+    }
+    return x;
+}
+
+// all lanes agree (wave is the whole workgroup: a barrier is one wave sync)
+__device__ __forceinline__ void wave_sync() { __syncthreads(); }
+
+// ------------------------------------------------------------ atomics
+// Agent scope = the whole GPU (all XCDs).  Relaxed operations are used for
+// counters whose value is the only data; acquire/release only where a
+// payload (node, cover bitmap) is published to another worker.
+
+__device__ __forceinline__ int ld_relaxed(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_acquire(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int add_relaxed(int* p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t add_relaxed(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t add_relaxed(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int add_acq_rel(int* p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int add_release(int* p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int min_relaxed(int* p, int v) {
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_acquire() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+__device__ __forceinline__ void fence_release() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+__device__ __forceinline__ bool cas_acquire(int* p, int expect, int desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_ACQUIRE,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_relaxed64(uint64_t* p, uint64_t expect, uint64_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void backoff(uint32_t& spins) {
+    if (spins < 8) {
+        __builtin_amdgcn_s_sleep(1);
+    } else {
+        __builtin_amdgcn_s_sleep(16);
+    }
+    ++spins;
+}
+
+// ----------------------------------------------- packed degrees in LDS
+// A degree array of element type D (uint8/uint16/uint32) lives in LDS as
+// 32-bit words; element v is bits [8*sizeof(D)*(v%per), +8*sizeof(D)) of
+// word v/per.  The all-ones value marks "in the cover"; 0 marks a vertex
+// with no remaining edge; anything else is the live degree.
+
+template <typename D>
+struct Deg {
+    static constexpr uint32_t per = 4u / sizeof(D);
+    static constexpr uint32_t bits = 8u * sizeof(D);
+    static constexpr uint32_t IN = (uint32_t)(D)(~(D)0);
+
+    __device__ static __forceinline__ uint32_t get(const D* a, uint32_t v) {
+        return (uint32_t)a[v];
+    }
+    __device__ static __forceinline__ void set(D* a, uint32_t v, uint32_t x) {
+        a[v] = (D)x;
+    }
+    __device__ static __forceinline__ bool live(uint32_t d) {
+        return d != 0u && d != IN;
+    }
+    // atomic decrement of a live entry (never underflows: callers only
+    // decrement once per live edge)
+    __device__ static __forceinline__ void dec(D* a, uint32_t v) {
+        uint32_t* w = reinterpret_cast<uint32_t*>(a);
+        atomicSub(&w[v / per], 1u << ((v % per) * bits));
+    }
+    // atomically mark v as in the cover; true if it was not marked before
+    __device__ static __forceinline__ bool mark_in(D* a, uint32_t v) {
+        uint32_t* w = reinterpret_cast<uint32_t*>(a);
+        uint32_t sh = (v % per) * bits;
+        uint32_t old = atomicOr(&w[v / per], IN << sh);
+        return ((old >> sh) & IN) != IN;
+    }
+};
+
+}  // namespace vc

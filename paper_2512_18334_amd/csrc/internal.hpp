@@ -1,0 +1,119 @@
+// internal.hpp -- structures shared by the libvc host runtime and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vc {
+
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr int INF = 0x3FFFFFFF;
+
+// Search-node slot in HBM (private stacks and the shared worklist): this
+// 32-byte header followed by the degree array (n_pad elements of the degree
+// type).  The degree array is the node's whole state (Sec. IV-A): entry 0 =
+// no remaining edge, all-ones = in the cover, else the live degree.
+struct SlotHdr {
+    int32_t s;         // |S| counted in the node's scope
+    int32_t scope;     // registry entry of the scope (0 = the root)
+    uint32_t branch_v; // NONE, or: first put N(branch_v) into the cover
+    uint32_t nlive;    // live vertices when stored (diagnostic)
+    uint32_t pad[4];
+};
+static_assert(sizeof(SlotHdr) == 32, "slot header is 32 bytes");
+
+// Component branch registry entry (Sec. III-C).  A child entry (a component,
+// or the root scope at index 0) holds {Best, LiveNodes, ParentIdx}; a parent
+// entry (a node that branched on components) holds {Sum, LiveComps,
+// AncestorIdx}.  Entries of one branch are contiguous: parent p, then its
+// children p+1 .. p+nchild.  Every entry owns one cover bitmap: a child's
+// best cover found so far, a parent's vertices taken before the split.
+struct RegEntry {
+    int best;       // child: Best          | parent: Sum
+    int live;       // child: LiveNodes     | parent: LiveComps
+    int up;         // child: ParentIdx     | parent: AncestorIdx (a child/root)
+    int lock;       // guards the cover bitmap
+    int cover_size; // vertices in the bitmap (INF: no attained cover yet)
+    int nchild;     // parent: number of children
+    int size;       // child: vertices of the component
+    int pad;
+};
+static_assert(sizeof(RegEntry) == 32, "registry entry is 32 bytes");
+
+// Control block (one per solve), fields on separate 128-byte lines.
+struct Ctl {
+    uint64_t wl_head;
+    uint64_t _p0[15];
+    uint64_t wl_tail;
+    uint64_t _p1[15];
+    int outstanding;  // queued nodes + busy workers
+    int _p2[31];
+    int idle;         // workers waiting for work
+    int _p3[31];
+    int done;         // stop flag (PVC answer found, error, limit)
+    int err;          // vc_status of a device-side failure
+    uint32_t reg_next;
+    int _p4[29];
+    uint64_t nodes;   // statistics
+    uint64_t comp_branches;
+    uint64_t components;
+    uint64_t donations;
+    uint64_t pushes;
+    uint64_t _p5[11];
+};
+
+struct SearchArgs {
+    uint32_t n;           // vertices of the induced subgraph
+    uint32_t n_pad;       // degree array elements (multiple of 64)
+    const uint32_t* off;  // CSR of the induced subgraph
+    const void* col;
+    uint32_t slot_bytes;
+    uint32_t stack_depth;
+    uint8_t* stacks;      // [workers][stack_depth][slot_bytes]
+    uint8_t* wl_slots;    // [wl_cap][slot_bytes]
+    uint64_t* wl_seq;     // [wl_cap]
+    uint32_t wl_cap;
+    uint32_t reg_cap;
+    Ctl* ctl;
+    RegEntry* reg;
+    uint32_t* bitmaps;    // [reg_cap][bm_words]
+    uint32_t bm_words;
+    uint32_t lds_L, lds_Q, lds_R, lds_VB, lds_PB, lds_misc, lds_bytes;
+    int pvc;              // 1: parameterized (stop once the root is <= k)
+    int k;
+    uint32_t flags;       // VC_OPT_* ablation switches
+    uint32_t donate_slack;
+    uint64_t node_limit;  // 0: none
+    uint64_t watchdog_ticks;  // idle wait limit in wall_clock64() ticks
+};
+
+// LDS layout of one worker for n vertices and degree element size sd.
+struct LdsPlan {
+    uint32_t L, Q, R, VB, PB, misc, bytes;
+};
+inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd) {
+    LdsPlan p;
+    uint32_t at = n_pad * sd;
+    at = (at + 15u) & ~15u;
+    p.L = at; at += 4u * n_pad;
+    p.Q = at; at += 4u * n_pad;
+    p.R = at; at += 4u * (2u * n_pad + 64u);
+    uint32_t bw = (n_pad + 31u) / 32u;
+    p.VB = at; at += 4u * bw;
+    p.PB = at; at += 4u * bw;
+    p.misc = at; at += 4u * 64u;
+    p.bytes = (at + 15u) & ~15u;
+    return p;
+}
+
+// ------------------------------------------------------ kernel launchers
+// (defined in the .hip files; all launch on `st`)
+
+hipError_t launch_search(const SearchArgs& a, uint32_t deg_bytes, uint32_t col_bytes,
+                         uint32_t workers, hipStream_t st);
+hipError_t search_occupancy(uint32_t deg_bytes, uint32_t col_bytes, uint32_t lds_bytes,
+                            int* blocks_per_cu);
+hipError_t launch_search_init(const SearchArgs& a, int best0, uint32_t deg_bytes,
+                              const uint32_t* kdeg, hipStream_t st);
+
+}  // namespace vc

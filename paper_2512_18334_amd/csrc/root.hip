@@ -1,0 +1,530 @@
+// root.hip -- grid-wide passes over the input graph before the search:
+// CSR validation, degrees, the greedy initial bound (Sec. II-B), the root
+// reduction to a fixpoint (Sec. IV-B), inducing the subgraph on the
+// remaining vertices with narrow column ids, and assembling the final cover.
+// These kernels stream the CSR from HBM; each is a grid-stride loop with one
+// vertex per thread.
+#include "dev_common.hpp"
+#include "internal.hpp"
+#include "root.hpp"
+
+namespace vc {
+
+constexpr uint32_t RIN = 0xFFFFFFFFu;  // root degree array: in the cover
+
+__device__ __forceinline__ bool rlive(uint32_t d) { return d != 0u && d != RIN; }
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    // splitmix64 finaliser
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+// one atomic per wave: every lane of the block must call this
+__device__ __forceinline__ void wave_atomic_add(uint32_t* p, uint32_t x) {
+    x = wave_sum(x);
+    if ((threadIdx.x & 63u) == 0 && x) atomicAdd(p, x);
+}
+
+#define GRID_LOOP(i, n)                                                        \
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (n);          \
+         i += gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------- validation
+
+// offsets: off[0] == 0, non-decreasing, off[n] == nnz
+__global__ void k_check_offsets(uint32_t n, uint64_t nnz, const uint32_t* off, uint32_t* ctr) {
+    GRID_LOOP(v, n) {
+        if (off[v] > off[v + 1]) atomicOr(&ctr[CTR_INVALID], 1u);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (off[0] != 0u || (uint64_t)off[n] != nnz) atomicOr(&ctr[CTR_INVALID], 2u);
+    }
+}
+
+// rows: ids < n, no self-loop, no repeated entry; symmetric (the signed sum
+// of a hash of each unordered pair over all entries vanishes exactly when
+// every entry has its mirror, up to hash collisions)
+template <typename C>
+__global__ void k_check_rows(uint32_t n, const uint32_t* off, const C* col, uint32_t* ctr,
+                             unsigned long long* hsum) {
+    uint64_t acc = 0;
+    uint32_t bad = 0;
+    GRID_LOOP(v, n) {
+        const uint32_t r0 = off[v], r1 = off[v + 1];
+        bool sorted = true;
+        for (uint32_t e = r0; e < r1; ++e) {
+            uint32_t w = (uint32_t)col[e];
+            if (w >= n) { bad |= 4u; continue; }
+            if (w == v) bad |= 8u;
+            if (e > r0 && (uint32_t)col[e - 1] >= w) sorted = false;
+            uint64_t a = v < w ? v : w, b = v < w ? w : v;
+            uint64_t h = mix64(a * 0x9E3779B97F4A7C15ull + b);
+            acc += v < w ? h : (0ull - h);
+        }
+        if (!sorted) {
+            if (r1 - r0 <= 512u) {
+                for (uint32_t e = r0; e < r1; ++e)
+                    for (uint32_t f = e + 1; f < r1; ++f)
+                        if (col[e] == col[f]) bad |= 16u;
+            } else {
+                bad |= 32u;  // long unsorted row: repeated entries not checked
+            }
+        }
+    }
+    if (bad & ~32u) atomicOr(&ctr[CTR_INVALID], bad & ~32u);
+    if (bad & 32u) atomicOr(&ctr[CTR_UNCHECKED], 1u);
+    acc = wave_sum64(acc);
+    if ((threadIdx.x & 63u) == 0 && acc) atomicAdd(hsum, (unsigned long long)acc);
+}
+
+// ------------------------------------------------------------- degrees
+
+__global__ void k_init(uint32_t n, const uint32_t* off, uint32_t* rdeg, uint32_t* gdeg,
+                       uint8_t* gin, uint8_t* addf, uint8_t* newly) {
+    GRID_LOOP(v, n) {
+        uint32_t d = off[v + 1] - off[v];
+        rdeg[v] = d;
+        gdeg[v] = d;
+        gin[v] = 0;
+        addf[v] = 0;
+        newly[v] = 0;
+    }
+}
+
+// ------------------------------------------------------------- greedy
+// Parallel max-degree greedy: each round takes every vertex whose key
+// (degree, then lower id) beats all its live neighbours' keys; these form
+// an independent set, so taking them together is well defined.
+
+template <typename C>
+__global__ void k_greedy_select(uint32_t n, const uint32_t* off, const C* col,
+                                const uint32_t* gdeg, uint8_t* sel, uint32_t* ctr_live) {
+    uint32_t live = 0;
+    GRID_LOOP(v, n) {
+        const uint32_t d = gdeg[v];
+        if (d == 0) continue;
+        ++live;
+        const uint64_t kv = ((uint64_t)d << 32) | (uint32_t)~v;
+        bool top = true;
+        for (uint32_t e = off[v]; e < off[v + 1] && top; ++e) {
+            uint32_t u = (uint32_t)col[e];
+            uint32_t du = gdeg[u];
+            if (du && (((uint64_t)du << 32) | (uint32_t)~u) > kv) top = false;
+        }
+        if (top) sel[v] = 1;
+    }
+    wave_atomic_add(ctr_live, live);
+}
+
+template <typename C>
+__global__ void k_greedy_apply(uint32_t n, const uint32_t* off, const C* col, uint32_t* gdeg,
+                               uint8_t* sel, uint8_t* gin, const uint32_t* ctr_live,
+                               uint32_t* ctr_size) {
+    if (*ctr_live == 0) return;
+    uint32_t taken = 0;
+    GRID_LOOP(v, n) {
+        if (!sel[v]) continue;
+        sel[v] = 0;
+        gin[v] = 1;
+        ++taken;
+        for (uint32_t e = off[v]; e < off[v + 1]; ++e) {
+            uint32_t u = (uint32_t)col[e];
+            if (gdeg[u]) atomicSub(&gdeg[u], 1u);
+        }
+        gdeg[v] = 0;
+    }
+    wave_atomic_add(ctr_size, taken);
+}
+
+// ------------------------------------------------------------- root reduce
+// One round = decide (rules on the state before the round, with the same
+// tie-breaks as the search kernel), mark (flags -> in the cover), remove
+// edges.  The bound is best0 - |S_root| - 1.
+
+template <typename C>
+__device__ __forceinline__ bool r_adjacent(const uint32_t* off, const C* col, uint32_t u,
+                                           uint32_t w) {
+    uint32_t a = u, b = w;
+    if (off[w + 1] - off[w] < off[u + 1] - off[u]) { a = w; b = u; }
+    for (uint32_t e = off[a]; e < off[a + 1]; ++e)
+        if ((uint32_t)col[e] == b) return true;
+    return false;
+}
+
+template <typename C>
+__global__ void k_reduce_decide(uint32_t n, const uint32_t* off, const C* col,
+                                const uint32_t* rdeg, uint8_t* addf, uint32_t* ctr,
+                                uint32_t round, int best0) {
+    const int s = (int)ctr[CTR_SROOT];
+    const int64_t b = (int64_t)best0 - s - 1;
+    uint32_t fired = 0;
+    if (s >= best0) return;
+    GRID_LOOP(v, n) {
+        const uint32_t d = rdeg[v];
+        if (!rlive(d)) continue;
+        if ((int64_t)d > b) {
+            addf[v] = 1;
+            ++fired;
+            continue;
+        }
+        if (d > 2u) continue;
+        uint32_t u = NONE, w = NONE, got = 0;
+        for (uint32_t e = off[v]; e < off[v + 1] && got < d; ++e) {
+            uint32_t x = (uint32_t)col[e];
+            if (rlive(rdeg[x])) {
+                if (got == 0) u = x; else w = x;
+                ++got;
+            }
+        }
+        if (got < d) continue;
+        if (d == 1u) {
+            if (!(rdeg[u] == 1u && u < v)) {
+                addf[u] = 1;
+                ++fired;
+            }
+        } else if (r_adjacent(off, col, u, w)) {
+            if (!(rdeg[u] == 2u && u < v) && !(rdeg[w] == 2u && w < v)) {
+                addf[u] = 1;
+                addf[w] = 1;
+                ++fired;
+            }
+        }
+    }
+    wave_atomic_add(&ctr[CTR_FIRED + (round & 1u)], fired);
+}
+
+__global__ void k_reduce_mark(uint32_t n, uint32_t* rdeg, uint8_t* addf, uint8_t* newly,
+                              uint32_t* ctr, uint32_t round) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[CTR_FIRED + ((round + 1u) & 1u)] = 0;
+    if (ctr[CTR_FIRED + (round & 1u)] == 0) return;
+    uint32_t added = 0;
+    GRID_LOOP(v, n) {
+        if (!addf[v]) continue;
+        addf[v] = 0;
+        if (rlive(rdeg[v])) {
+            rdeg[v] = RIN;
+            newly[v] = 1;
+            ++added;
+        }
+    }
+    wave_atomic_add(&ctr[CTR_SROOT], added);
+}
+
+template <typename C>
+__global__ void k_reduce_remove(uint32_t n, const uint32_t* off, const C* col, uint32_t* rdeg,
+                                uint8_t* newly) {
+    GRID_LOOP(v, n) {
+        if (!newly[v]) continue;
+        newly[v] = 0;
+        for (uint32_t e = off[v]; e < off[v + 1]; ++e) {
+            uint32_t u = (uint32_t)col[e];
+            if (rlive(rdeg[u])) atomicSub(&rdeg[u], 1u);
+        }
+    }
+}
+
+// ------------------------------------------------------------- scan
+// Exclusive prefix sum, three passes: per-block totals, one block scans the
+// totals, per-block scan plus its offset.  2048 items per 256-thread block.
+
+constexpr uint32_t SCAN_T = 256, SCAN_PER = 8, SCAN_ITEMS = SCAN_T * SCAN_PER;
+
+template <typename T>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* sh, uint32_t* total) {
+    const uint32_t w = threadIdx.x >> 6, l = threadIdx.x & 63u;
+    uint32_t incl = wave_incl_scan(x);
+    if (l == 63) sh[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (uint32_t i = 0; i < SCAN_T / 64; ++i) {
+        if (i < w) pre += sh[i];
+        tot += sh[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + incl - x;
+}
+
+template <typename T>
+__global__ void k_scan_totals(const T* in, uint32_t N, uint32_t* sums) {
+    __shared__ uint32_t sh[SCAN_T / 64];
+    const uint32_t base = blockIdx.x * SCAN_ITEMS + threadIdx.x * SCAN_PER;
+    uint32_t x = 0;
+    for (uint32_t j = 0; j < SCAN_PER; ++j)
+        if (base + j < N) x += (uint32_t)in[base + j];
+    uint32_t tot;
+    block_excl_scan<T>(x, sh, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_sums(uint32_t* sums, uint32_t nb) {
+    __shared__ uint32_t sh[SCAN_T / 64];
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nb; base += SCAN_T) {
+        uint32_t i = base + threadIdx.x;
+        uint32_t x = i < nb ? sums[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan<uint32_t>(x, sh, &tot);
+        if (i < nb) sums[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+template <typename T>
+__global__ void k_scan_apply(const T* in, uint32_t N, const uint32_t* sums, uint32_t* out,
+                             uint32_t nb) {
+    __shared__ uint32_t sh[SCAN_T / 64];
+    const uint32_t base = blockIdx.x * SCAN_ITEMS + threadIdx.x * SCAN_PER;
+    uint32_t v[SCAN_PER];
+    uint32_t x = 0;
+    for (uint32_t j = 0; j < SCAN_PER; ++j) {
+        v[j] = base + j < N ? (uint32_t)in[base + j] : 0u;
+        x += v[j];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<T>(x, sh, &tot) + sums[blockIdx.x];
+    for (uint32_t j = 0; j < SCAN_PER; ++j) {
+        if (base + j < N) out[base + j] = ex;
+        ex += v[j];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[N] = sums[nb];
+}
+
+// ------------------------------------------------------------- induce
+
+__global__ void k_live_flags(uint32_t n, const uint32_t* rdeg, uint32_t* flag) {
+    GRID_LOOP(v, n) flag[v] = rlive(rdeg[v]) ? 1u : 0u;
+}
+
+__global__ void k_induce_deg(uint32_t n, const uint32_t* rdeg, const uint32_t* newid,
+                             uint32_t* kdeg, uint32_t* oldid, uint32_t* ctr) {
+    uint32_t mx = 0;
+    GRID_LOOP(v, n) {
+        const uint32_t d = rdeg[v];
+        if (!rlive(d)) continue;
+        const uint32_t i = newid[v];
+        kdeg[i] = d;
+        oldid[i] = v;
+        mx = d > mx ? d : mx;
+    }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63u) == 0 && mx) atomicMax(&ctr[CTR_MAXDEG], mx);
+}
+
+template <typename C, typename CO>
+__global__ void k_induce_cols(uint32_t np, const uint32_t* off, const C* col,
+                              const uint32_t* rdeg, const uint32_t* newid,
+                              const uint32_t* oldid, const uint32_t* koff, CO* kcol) {
+    GRID_LOOP(i, np) {
+        const uint32_t v = oldid[i];
+        uint32_t pos = koff[i];
+        const uint32_t end = koff[i + 1];
+        for (uint32_t e = off[v]; e < off[v + 1] && pos < end; ++e) {
+            uint32_t u = (uint32_t)col[e];
+            if (rlive(rdeg[u])) kcol[pos++] = (CO)newid[u];
+        }
+    }
+}
+
+// ------------------------------------------------------------- cover
+
+// flags[v] = 1 for the final cover: root-forced vertices plus the kernel
+// cover (mapped back) when the search improved on the greedy bound, else the
+// greedy cover itself.
+__global__ void k_cover_base(uint32_t n, const uint32_t* rdeg, const uint8_t* gin,
+                             int improved, uint32_t* flags) {
+    GRID_LOOP(v, n) flags[v] = improved ? (rdeg[v] == RIN ? 1u : 0u) : (uint32_t)gin[v];
+}
+
+__global__ void k_cover_kernel(uint32_t np, const uint32_t* oldid, const uint32_t* bitmap,
+                               uint32_t* flags) {
+    GRID_LOOP(i, np) {
+        if ((bitmap[i >> 5] >> (i & 31u)) & 1u) flags[oldid[i]] = 1u;
+    }
+}
+
+__global__ void k_cover_list(uint32_t n, const uint32_t* flags, const uint32_t* pos,
+                             uint32_t* out) {
+    GRID_LOOP(v, n) {
+        if (flags[v]) out[pos[v]] = v;
+    }
+}
+
+// ============================================================ launchers
+
+static inline uint32_t grid_for(uint64_t n, uint32_t t = 256) {
+    uint64_t b = (n + t - 1) / t;
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return (uint32_t)b;
+}
+
+hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* hsum,
+                         hipStream_t st, uint32_t* bad_host) {
+    hipError_t e;
+    hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, g.nnz,
+                       g.off, ctr);
+    if ((e = hipGetLastError())) return e;
+    uint32_t bad = 0;
+    if ((e = hipMemcpyAsync(&bad, ctr + CTR_INVALID, 4, hipMemcpyDeviceToHost, st))) return e;
+    if ((e = hipStreamSynchronize(st))) return e;
+    if (bad) {
+        *bad_host = bad;
+        return hipSuccess;
+    }
+    if (g.col_bytes == 2)
+        hipLaunchKernelGGL(k_check_rows<uint16_t>, dim3(grid_for(g.n)), dim3(256), 0, st, g.n,
+                           g.off, (const uint16_t*)g.col, ctr, hsum);
+    else
+        hipLaunchKernelGGL(k_check_rows<uint32_t>, dim3(grid_for(g.n)), dim3(256), 0, st, g.n,
+                           g.off, (const uint32_t*)g.col, ctr, hsum);
+    if ((e = hipGetLastError())) return e;
+    unsigned long long hs = 0;
+    if ((e = hipMemcpyAsync(&bad, ctr + CTR_INVALID, 4, hipMemcpyDeviceToHost, st))) return e;
+    if ((e = hipMemcpyAsync(&hs, hsum, 8, hipMemcpyDeviceToHost, st))) return e;
+    if ((e = hipStreamSynchronize(st))) return e;
+    if (hs != 0) bad |= 64u;
+    *bad_host = bad;
+    return hipSuccess;
+}
+
+hipError_t root_init(const RootGraph& g, const RootBufs& b, hipStream_t st) {
+    hipLaunchKernelGGL(k_init, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, g.off, b.rdeg, b.gdeg,
+                       b.gin, b.addf, b.newly);
+    return hipGetLastError();
+}
+
+template <typename C>
+static hipError_t greedy_t(const RootGraph& g, const RootBufs& b, hipStream_t st,
+                           uint32_t* rounds) {
+    const C* col = (const C*)g.col;
+    hipError_t e;
+    const uint32_t grid = grid_for(g.n);
+    for (uint32_t r = 0;; r += 4) {
+        for (uint32_t j = 0; j < 4; ++j) {
+            uint32_t* live = b.ctr + CTR_GLIVE + ((r + j) & 1u);
+            if ((e = hipMemsetAsync(live, 0, 4, st))) return e;
+            hipLaunchKernelGGL(k_greedy_select<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
+                               b.gdeg, b.addf, live);
+            hipLaunchKernelGGL(k_greedy_apply<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
+                               b.gdeg, b.addf, b.gin, live, b.ctr + CTR_GSIZE);
+        }
+        if ((e = hipGetLastError())) return e;
+        uint32_t live = 0;
+        if ((e = hipMemcpyAsync(&live, b.ctr + CTR_GLIVE + ((r + 3) & 1u), 4,
+                                hipMemcpyDeviceToHost, st)))
+            return e;
+        if ((e = hipStreamSynchronize(st))) return e;
+        if (live == 0 || r > 4 * g.n + 8) {
+            *rounds = r + 4;
+            return hipSuccess;
+        }
+    }
+}
+
+hipError_t root_greedy(const RootGraph& g, const RootBufs& b, hipStream_t st, uint32_t* rounds) {
+    return g.col_bytes == 2 ? greedy_t<uint16_t>(g, b, st, rounds)
+                            : greedy_t<uint32_t>(g, b, st, rounds);
+}
+
+template <typename C>
+static hipError_t reduce_t(const RootGraph& g, const RootBufs& b, int best0, hipStream_t st,
+                           uint32_t max_rounds, uint32_t* rounds) {
+    const C* col = (const C*)g.col;
+    hipError_t e;
+    const uint32_t grid = grid_for(g.n);
+    uint32_t r = 0;
+    for (;;) {
+        for (uint32_t j = 0; j < 4; ++j, ++r) {
+            hipLaunchKernelGGL(k_reduce_decide<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
+                               b.rdeg, b.addf, b.ctr, r, best0);
+            hipLaunchKernelGGL(k_reduce_mark, dim3(grid), dim3(256), 0, st, g.n, b.rdeg, b.addf,
+                               b.newly, b.ctr, r);
+            hipLaunchKernelGGL(k_reduce_remove<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
+                               b.rdeg, b.newly);
+        }
+        if ((e = hipGetLastError())) return e;
+        uint32_t fired = 0;
+        if ((e = hipMemcpyAsync(&fired, b.ctr + CTR_FIRED + ((r - 1) & 1u), 4,
+                                hipMemcpyDeviceToHost, st)))
+            return e;
+        if ((e = hipStreamSynchronize(st))) return e;
+        if (fired == 0 || r >= max_rounds) break;
+    }
+    *rounds = r;
+    return hipSuccess;
+}
+
+hipError_t root_reduce(const RootGraph& g, const RootBufs& b, int best0, hipStream_t st,
+                       uint32_t max_rounds, uint32_t* rounds) {
+    return g.col_bytes == 2 ? reduce_t<uint16_t>(g, b, best0, st, max_rounds, rounds)
+                            : reduce_t<uint32_t>(g, b, best0, st, max_rounds, rounds);
+}
+
+hipError_t scan_u32(const uint32_t* in, uint32_t N, uint32_t* out, uint32_t* tmp,
+                    hipStream_t st) {
+    const uint32_t nb = (N + SCAN_ITEMS - 1) / SCAN_ITEMS ? (N + SCAN_ITEMS - 1) / SCAN_ITEMS : 1;
+    hipLaunchKernelGGL(k_scan_totals<uint32_t>, dim3(nb), dim3(SCAN_T), 0, st, in, N, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_apply<uint32_t>, dim3(nb), dim3(SCAN_T), 0, st, in, N, tmp, out, nb);
+    return hipGetLastError();
+}
+
+hipError_t root_induce_a(const RootGraph& g, const RootBufs& b, hipStream_t st) {
+    hipLaunchKernelGGL(k_live_flags, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, b.rdeg, b.flags);
+    hipError_t e = scan_u32(b.flags, g.n, b.newid, b.scan_tmp, st);
+    if (e) return e;
+    hipLaunchKernelGGL(k_induce_deg, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, b.rdeg, b.newid,
+                       b.kdeg, b.oldid, b.ctr);
+    return hipGetLastError();
+}
+
+hipError_t root_induce_b(const RootGraph& g, const RootBufs& b, uint32_t np, uint32_t kcol_bytes,
+                         hipStream_t st) {
+    hipError_t e = scan_u32(b.kdeg, np, b.koff, b.scan_tmp, st);
+    if (e) return e;
+    const uint32_t grid = grid_for(np);
+    if (g.col_bytes == 2) {
+        if (kcol_bytes == 2)
+            hipLaunchKernelGGL((k_induce_cols<uint16_t, uint16_t>), dim3(grid), dim3(256), 0, st,
+                               np, g.off, (const uint16_t*)g.col, b.rdeg, b.newid, b.oldid, b.koff,
+                               (uint16_t*)b.kcol);
+        else
+            hipLaunchKernelGGL((k_induce_cols<uint16_t, uint32_t>), dim3(grid), dim3(256), 0, st,
+                               np, g.off, (const uint16_t*)g.col, b.rdeg, b.newid, b.oldid, b.koff,
+                               (uint32_t*)b.kcol);
+    } else {
+        if (kcol_bytes == 2)
+            hipLaunchKernelGGL((k_induce_cols<uint32_t, uint16_t>), dim3(grid), dim3(256), 0, st,
+                               np, g.off, (const uint32_t*)g.col, b.rdeg, b.newid, b.oldid, b.koff,
+                               (uint16_t*)b.kcol);
+        else
+            hipLaunchKernelGGL((k_induce_cols<uint32_t, uint32_t>), dim3(grid), dim3(256), 0, st,
+                               np, g.off, (const uint32_t*)g.col, b.rdeg, b.newid, b.oldid, b.koff,
+                               (uint32_t*)b.kcol);
+    }
+    return hipGetLastError();
+}
+
+hipError_t root_cover(const RootGraph& g, const RootBufs& b, uint32_t np, int improved,
+                      const uint32_t* root_bitmap, hipStream_t st) {
+    hipLaunchKernelGGL(k_cover_base, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, b.rdeg, b.gin,
+                       improved, b.flags);
+    if (improved && np)
+        hipLaunchKernelGGL(k_cover_kernel, dim3(grid_for(np)), dim3(256), 0, st, np, b.oldid,
+                           root_bitmap, b.flags);
+    hipError_t e = scan_u32(b.flags, g.n, b.newid, b.scan_tmp, st);
+    if (e) return e;
+    hipLaunchKernelGGL(k_cover_list, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, b.flags, b.newid,
+                       b.cover);
+    return hipGetLastError();
+}
+
+}  // namespace vc

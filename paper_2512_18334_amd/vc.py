@@ -1,0 +1,229 @@
+"""Python binding of libvc (include/vc.h): argument marshalling only.
+
+Every step of a solve runs in the HIP kernels of libvc.so; this module only
+builds the C structs, passes pointers and turns status codes into
+exceptions.  PyTorch is used for device memory (graphs made resident in HBM)
+and for streams.  There is no fallback: if libvc.so is missing or cannot be
+loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvc.so")
+
+VC_OK, VC_EINVAL, VC_ENOMEM, VC_EDEVICE = 0, -1, -2, -3
+VC_EAGAIN, VC_ETIMEDOUT, VC_ECANCELED, VC_ERANGE = -4, -5, -6, -7
+VC_CSR_DEVICE = 1
+VC_OPT_NO_COMPONENTS = 1
+VC_OPT_NO_LOAD_BALANCE = 2
+VC_OPT_VALIDATE_SKIP = 4
+
+EXPORTS = ["vc_ctx_create", "vc_ctx_destroy", "vc_validate", "vc_min",
+           "vc_param", "vc_last_stats", "vc_status_str"]
+
+
+class vc_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("nnz", ctypes.c_uint64),
+                ("offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p),
+                ("col_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class vc_opts(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_uint32), ("donate_slack", ctypes.c_uint32),
+                ("worklist_cap", ctypes.c_uint32), ("registry_cap", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64), ("node_limit", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32)]
+
+
+class vc_stats(ctypes.Structure):
+    _fields_ = [("tree_nodes", ctypes.c_uint64),
+                ("component_branches", ctypes.c_uint64),
+                ("components", ctypes.c_uint64), ("donations", ctypes.c_uint64),
+                ("pushes", ctypes.c_uint64),
+                ("n_input", ctypes.c_uint32), ("n_kernel", ctypes.c_uint32),
+                ("nnz_kernel", ctypes.c_uint64), ("forced_root", ctypes.c_uint32),
+                ("greedy_size", ctypes.c_uint32),
+                ("max_degree_kernel", ctypes.c_uint32),
+                ("deg_bytes", ctypes.c_uint32), ("workers", ctypes.c_uint32),
+                ("root_rounds", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint32),
+                ("bitmap_bytes", ctypes.c_uint32), ("ms_root", ctypes.c_double),
+                ("ms_induce", ctypes.c_double), ("ms_search", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
+class VCError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"libvc {what}: {status_str(status)} ({status})")
+
+
+_lib = None
+
+
+def load():
+    """Load libvc.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first "
+                          "(python -m paper_2512_18334_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    p = ctypes.c_void_p
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.vc_ctx_create.restype = ctypes.c_int
+    lib.vc_ctx_create.argtypes = [ctypes.c_int, p, ctypes.POINTER(vc_opts),
+                                  ctypes.POINTER(p)]
+    lib.vc_ctx_destroy.restype = ctypes.c_int
+    lib.vc_ctx_destroy.argtypes = [p]
+    lib.vc_validate.restype = ctypes.c_int
+    lib.vc_validate.argtypes = [p, ctypes.POINTER(vc_csr)]
+    lib.vc_min.restype = ctypes.c_int
+    lib.vc_min.argtypes = [p, ctypes.POINTER(vc_csr), u32p, u32p, u32p]
+    lib.vc_param.restype = ctypes.c_int
+    lib.vc_param.argtypes = [p, ctypes.POINTER(vc_csr), ctypes.c_uint32,
+                             ctypes.POINTER(ctypes.c_int), u32p, u32p]
+    lib.vc_last_stats.restype = ctypes.c_int
+    lib.vc_last_stats.argtypes = [p, ctypes.POINTER(vc_stats)]
+    lib.vc_status_str.restype = ctypes.c_char_p
+    lib.vc_status_str.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def status_str(s: int) -> str:
+    return load().vc_status_str(int(s)).decode()
+
+
+def _check(st: int, what: str):
+    if st != VC_OK:
+        raise VCError(st, what)
+
+
+@dataclass
+class DeviceGraph:
+    """A CSR graph resident in device memory (torch tensors keep it alive)."""
+    n: int
+    nnz: int
+    offsets: object       # torch.int32 tensor, bytes of uint32 offsets
+    cols: object          # torch.int16 / torch.int32 tensor
+    col_bytes: int
+
+    @classmethod
+    def from_graph(cls, g, device="cuda"):
+        import torch
+        off = torch.from_numpy(np.ascontiguousarray(g.offsets, np.uint32).view(np.int32))
+        cdt = np.int16 if g.col_bytes == 2 else np.int32
+        col = torch.from_numpy(np.ascontiguousarray(g.cols).view(cdt))
+        return cls(g.n, g.nnz, off.to(device), col.to(device), g.col_bytes)
+
+    def csr(self) -> vc_csr:
+        return vc_csr(self.n, self.nnz, self.offsets.data_ptr(),
+                      self.cols.data_ptr() if self.nnz else None,
+                      self.col_bytes, VC_CSR_DEVICE)
+
+
+def host_csr(g):
+    """vc_csr for a host graph plus the arrays that must stay alive."""
+    off = np.ascontiguousarray(g.offsets, dtype=np.uint32)
+    cols = np.ascontiguousarray(g.cols)
+    if cols.dtype not in (np.uint16, np.uint32):
+        cols = cols.astype(np.uint32)
+    c = vc_csr(int(g.n), int(off[-1]) if off.size else 0,
+               off.ctypes.data, cols.ctypes.data if cols.size else None,
+               int(cols.dtype.itemsize), 0)
+    return c, (off, cols)
+
+
+@dataclass
+class Result:
+    size: int | None      # MVC size (None for PVC)
+    yes: bool | None      # PVC answer (None for MVC)
+    cover: np.ndarray     # cover vertex ids, ascending
+    stats: dict
+
+
+class Solver:
+    """One libvc context on a HIP device."""
+
+    def __init__(self, device: int = 0, stream=None, workers: int = 0,
+                 donate_slack: int = 0, worklist_cap: int = 0,
+                 registry_cap: int = 0, hbm_budget: int = 0,
+                 node_limit: int = 0, flags: int = 0, watchdog_ms: int = 0):
+        lib = load()
+        self._opts = vc_opts(workers, donate_slack, worklist_cap, registry_cap,
+                             hbm_budget, node_limit, flags, watchdog_ms)
+        h = ctypes.c_void_p()
+        st = lib.vc_ctx_create(int(device), stream, ctypes.byref(self._opts),
+                               ctypes.byref(h))
+        _check(st, "vc_ctx_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().vc_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @staticmethod
+    def _csr(g):
+        if isinstance(g, DeviceGraph):
+            return g.csr(), (g,)
+        return host_csr(g)
+
+    def validate(self, g) -> int:
+        c, keep = self._csr(g)
+        return load().vc_validate(self._h, ctypes.byref(c))
+
+
+    def stats(self) -> dict:
+        s = vc_stats()
+        _check(load().vc_last_stats(self._h, ctypes.byref(s)), "vc_last_stats")
+        return {f: getattr(s, f) for f, _ in vc_stats._fields_}
+
+    def mvc(self, g, want_cover: bool = True) -> Result:
+        c, keep = self._csr(g)
+        n = int(c.n)
+        size = ctypes.c_uint32(0)
+        clen = ctypes.c_uint32(0)
+        cov = np.zeros(max(n, 1), np.uint32)
+        cp = cov.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if want_cover else None
+        st = load().vc_min(self._h, ctypes.byref(c), ctypes.byref(size), cp,
+                           ctypes.byref(clen))
+        _check(st, "vc_min")
+        return Result(int(size.value), None, cov[:clen.value].copy(), self.stats())
+
+    def pvc(self, g, k: int, want_cover: bool = True) -> Result:
+        c, keep = self._csr(g)
+        n = int(c.n)
+        yes = ctypes.c_int(0)
+        clen = ctypes.c_uint32(0)
+        cov = np.zeros(max(n, 1), np.uint32)
+        cp = cov.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if want_cover else None
+        st = load().vc_param(self._h, ctypes.byref(c), int(k), ctypes.byref(yes),
+                             cp, ctypes.byref(clen))
+        _check(st, "vc_param")
+        return Result(None, bool(yes.value), cov[:clen.value].copy(), self.stats())
+
+
+def validate_host(g) -> int:
+    """Exact host-side CSR check (no device or context needed)."""
+    c, keep = host_csr(g)
+    return load().vc_validate(None, ctypes.byref(c))

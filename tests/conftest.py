@@ -18,3 +18,13 @@ def pytest_configure(config):
 def orc():
     import oracle
     return oracle
+
+
+@pytest.fixture(scope="session")
+def libvc():
+    """The built libvc.so (built once if it is not there yet)."""
+    from paper_2512_18334_amd import vc
+    if not os.path.exists(vc.LIB_PATH):
+        from paper_2512_18334_amd import build
+        build.build()
+    return vc.load()

@@ -1,0 +1,232 @@
+"""GPU path vs the CPU oracle and closed forms, through the C ABI.
+
+Every expected value comes from a closed form or from the oracle (never from
+the GPU).  MVC sizes and PVC answers must agree exactly; every returned cover
+is checked on every edge and for its size.  Which cover is returned is not
+unique and is not compared.
+"""
+import numpy as np
+import pytest
+
+from paper_2512_18334_amd import graphgen as gg
+from paper_2512_18334_amd import vc
+from tests.helpers import assert_cover
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver(libvc):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    s = vc.Solver(0)
+    yield s
+    s.close()
+
+
+def gpu_mvc(solver, g, expected):
+    r = solver.mvc(g)
+    assert r.size == expected, (g.name, r.size, expected)
+    assert_cover(g, r.cover, size=expected)
+    return r
+
+
+def gpu_pvc_threshold(solver, g, mvc, ks=None):
+    for k in (ks if ks is not None else [mvc - 1, mvc, mvc + 1]):
+        if k < 0:
+            continue
+        r = solver.pvc(g, k)
+        assert r.yes == (k >= mvc), (g.name, k, mvc, r.yes)
+        if r.yes:
+            assert_cover(g, r.cover, at_most=k)
+        else:
+            assert r.cover.size == 0
+
+
+# ----------------------------------------------------------- closed forms
+
+def test_closed_forms(solver):
+    cases = []
+    cases += [(gg.path(n), n // 2) for n in range(1, 21)]
+    cases += [(gg.cycle(n), (n + 1) // 2) for n in range(3, 21)]
+    cases += [(gg.complete(n), max(n - 1, 0)) for n in range(1, 13)]
+    cases += [(gg.complete_bipartite(a, b), min(a, b))
+              for a, b in [(1, 1), (2, 5), (3, 3), (4, 7), (6, 6)]]
+    cases += [(gg.star(k), 1) for k in (1, 3, 40)]
+    cases += [(gg.petersen(), 6)]
+    cases += [(gg.grid(a, b), a * b // 2) for a, b in [(2, 3), (4, 4), (5, 6)]]
+    cases += [(gg.hypercube(d), 1 << (d - 1)) for d in range(1, 6)]
+    for g, expect in cases:
+        gpu_mvc(solver, gg.relabel(g, 7), expect)
+
+
+def test_fig1_example(solver):
+    g = gg.fig1_tree()
+    r = gpu_mvc(solver, g, 3)
+    assert sorted(r.cover.tolist()) == [1, 4, 7]  # {b, e, h}
+    gpu_pvc_threshold(solver, g, 3)
+
+
+def test_empty_and_edgeless(solver):
+    for g in [gg.from_edges(0, [], []), gg.from_edges(1, [], []),
+              gg.from_edges(33, [], [])]:
+        r = solver.mvc(g)
+        assert r.size == 0 and r.cover.size == 0
+        assert solver.pvc(g, 0).yes
+
+
+def test_disjoint_union_of_simple_components(solver, orc):
+    g = gg.relabel(gg.disjoint_union([gg.cycle(9), gg.complete(6), gg.cycle(4),
+                                      gg.petersen(), gg.complete(4), gg.cycle(12)]), 3)
+    gpu_mvc(solver, g, 5 + 5 + 2 + 6 + 3 + 6)
+
+
+# ------------------------------------------------------- G(60, 0.1) workload
+
+@pytest.mark.parametrize("block", range(8))
+def test_gnp60_parity(solver, orc, block):
+    for seed in range(1 + 32 * block, 33 + 32 * block):
+        g = gg.config1_gnp60(seed)
+        gpu_mvc(solver, g, orc.mvc(g)["size"])
+
+
+def test_gnp60_pvc(solver, orc):
+    for seed in range(1, 33):
+        g = gg.config1_gnp60(seed)
+        gpu_pvc_threshold(solver, g, orc.mvc(g)["size"])
+
+
+def test_random_small_graphs(solver, orc):
+    r = gg.rng(777)
+    for i in range(200):
+        n = int(r.integers(6, 48))
+        p = float(r.uniform(0.04, 0.5))
+        g = gg.gnp(n, p, 5000 + i)
+        gpu_mvc(solver, g, orc.mvc(g)["size"])
+
+
+def test_device_resident_input(solver, orc):
+    for seed in (1, 2, 3):
+        g = gg.config1_gnp60(seed)
+        dg = vc.DeviceGraph.from_graph(g)
+        r = solver.mvc(dg)
+        assert r.size == orc.mvc(g)["size"]
+        assert_cover(g, r.cover, size=r.size)
+
+
+def test_device_validation_rejects(solver):
+    g = gg.petersen().with_cols(4)
+    bad = gg.Graph(g.n, g.offsets.copy(), g.cols.copy())
+    bad.cols[0] = 0  # self-loop
+    with pytest.raises(vc.VCError) as e:
+        solver.mvc(vc.DeviceGraph.from_graph(bad))
+    assert e.value.status == vc.VC_EINVAL
+    asym = gg.Graph(g.n, g.offsets.copy(), g.cols.copy())
+    row = set(asym.cols[asym.offsets[0]:asym.offsets[1]].tolist())
+    asym.cols[0] = next(x for x in range(1, g.n) if x not in row)
+    with pytest.raises(vc.VCError) as e:
+        solver.mvc(vc.DeviceGraph.from_graph(asym))
+    assert e.value.status == vc.VC_EINVAL
+
+
+# ------------------------------------------- component-splitting workload
+
+def test_blocks_hubs_small(solver, orc):
+    for seed in range(4):
+        g = gg.config2_blocks_hubs(seed=10 + seed, nblocks=6, bsize=48, nhubs=3,
+                                   per_block=12)
+        gpu_mvc(solver, g, orc.mvc(g)["size"])
+
+
+def test_blocks_hubs_full(solver, orc):
+    g = gg.config2_blocks_hubs()
+    expect = orc.mvc(g)["size"]
+    assert expect == 1077
+    r = gpu_mvc(solver, g, expect)
+    st = r.stats
+    assert st["deg_bytes"] == 2          # hub degree 600 needs 16 bits
+    assert st["component_branches"] > 0  # hubs out -> the blocks split
+    gpu_pvc_threshold(solver, g, expect)
+
+
+def test_ablation_switches_agree(solver, orc, libvc):
+    g = gg.config2_blocks_hubs(seed=21, nblocks=6, bsize=48, nhubs=3, per_block=12)
+    expect = orc.mvc(g)["size"]
+    for kw in [dict(flags=vc.VC_OPT_NO_COMPONENTS),
+               dict(flags=vc.VC_OPT_NO_LOAD_BALANCE),
+               dict(workers=1), dict(workers=3),
+               dict(registry_cap=64), dict(worklist_cap=8)]:
+        with vc.Solver(0, **kw) as s2:
+            gpu_mvc(s2, g, expect)
+
+
+def _hub_graph(hub_degree, seed):
+    """Cubic blocks plus one hub of exactly hub_degree neighbours, so that
+    the hub survives the root reduction (the cover is far larger)."""
+    r = gg.rng(seed)
+    nblocks, bsize = 24, 48
+    us, vs = [], []
+    for b in range(nblocks):
+        a, c = gg.random_regular(bsize, 3, r)
+        us.append(a + b * bsize)
+        vs.append(c + b * bsize)
+    hub = nblocks * bsize
+    t = r.choice(hub, size=hub_degree, replace=False)
+    us.append(np.full(hub_degree, hub))
+    vs.append(t)
+    return gg.relabel(gg.from_edges(hub + 1, np.concatenate(us), np.concatenate(vs)), seed)
+
+
+@pytest.mark.parametrize("hub_degree,deg_bytes", [(254, 1), (255, 2), (300, 2)])
+def test_degree_type_boundary(solver, orc, hub_degree, deg_bytes):
+    g = _hub_graph(hub_degree, 40 + hub_degree)
+    r = gpu_mvc(solver, g, orc.mvc(g)["size"])
+    if r.stats["n_kernel"]:
+        assert r.stats["max_degree_kernel"] == hub_degree
+        assert r.stats["deg_bytes"] == deg_bytes
+
+
+# ----------------------------------------------- large sparse PVC workload
+
+@pytest.fixture(scope="module")
+def chung_lu_full():
+    return gg.config3_chung_lu()
+
+
+def test_planted_power_law_pvc_full(solver, orc, chung_lu_full):
+    g = chung_lu_full
+    o = orc.mvc(g)
+    mvc = o["size"]
+    assert mvc <= g.planted.size
+    dg = vc.DeviceGraph.from_graph(g)
+    for k in (mvc - 1, mvc):
+        r = solver.pvc(dg, k)
+        assert r.yes == (k >= mvc)
+        if r.yes:
+            assert_cover(g, r.cover, at_most=k)
+    r = solver.mvc(dg)
+    assert r.size == mvc
+    assert_cover(g, r.cover, size=mvc)
+
+
+def test_planted_power_law_scaled(solver, orc):
+    for seed in (31, 32):
+        g = gg.chung_lu_planted(100_000, 500_000, 2.1, 6_000, seed=seed)
+        o = orc.mvc(g)
+        gpu_mvc(solver, g, o["size"])
+        gpu_pvc_threshold(solver, g, o["size"])
+
+
+# ------------------------------------------------------ batch-config sample
+
+def test_batch_config_tractable_sample(solver, orc):
+    gs = gg.config4_batch(count=48)
+    done = 0
+    for g in gs:
+        try:
+            o = orc.mvc(g, node_limit=200_000)
+        except orc.OracleLimit:
+            continue
+        gpu_mvc(solver, g, o["size"])
+        done += 1
+    assert done >= 10
