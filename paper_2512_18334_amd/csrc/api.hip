@@ -334,7 +334,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         HIPCHK(search_occupancy(deg_bytes, kcol_bytes, lp.bytes, &bpc));
         if (bpc < 1) return VC_ERANGE;
         uint32_t workers = c->opts.workers ? c->opts.workers : (uint32_t)(bpc * c->cus);
-        const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes;
+        const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes + 16u;
         uint32_t depth = std::min<uint32_t>(np, (uint32_t)kbest0) + np / 4u + 16u;
         const uint64_t budget = c->opts.hbm_budget ? c->opts.hbm_budget : (48ull << 30);
         const uint64_t per_worker = (uint64_t)depth * slot_bytes;
@@ -414,6 +414,29 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
             c->last = stv;
             return (vc_status)ctl.err;
         }
+        if (getenv("VC_DEBUG") && ctl.stale)
+            fprintf(stderr, "libvc: %llu stale worklist reads were retried\n",
+                    (unsigned long long)ctl.stale);
+        if (getenv("VC_DEBUG_REGISTRY")) {
+            // after a complete MVC search every counter must be back at 0
+            const uint32_t used = std::min<uint32_t>(ctl.reg_next, (uint32_t)reg_cap);
+            std::vector<RegEntry> ents(used);
+            HIPCHK(hipMemcpy(ents.data(), c->reg.p, sizeof(RegEntry) * used,
+                             hipMemcpyDeviceToHost));
+            uint32_t pos = 0, neg = 0, parents = 0;
+            for (uint32_t i = 4; i < used; ++i) {
+                const RegEntry& r = ents[i];
+                if (r.up < 0 && r.nchild == 0 && r.size == 0) continue;  // padding
+                if (r.nchild > 0) ++parents;
+                if (r.live > 0) ++pos;
+                if (r.live < 0) ++neg;
+            }
+            fprintf(stderr,
+                    "libvc registry: used=%u parents=%u live>0=%u live<0=%u outstanding=%d "
+                    "idle=%d root.best=%d root.cover=%d kbest0=%d done=%d\n",
+                    used, parents, pos, neg, ctl.outstanding, ctl.idle, root.best,
+                    root.cover_size, kbest0, ctl.done);
+        }
         if (root.best < kbest0) {
             if (root.cover_size != root.best) return VC_EDEVICE;  // internal invariant
             improved = true;
@@ -451,15 +474,28 @@ vc_status vc_ctx_create(int device, void* stream, const vc_opts* opts, vc_ctx** 
     if (!out) return VC_EINVAL;
     *out = nullptr;
     int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    hipError_t he = hipGetDeviceCount(&count);
+    if (he != hipSuccess || device < 0 || device >= count) {
+        if (getenv("VC_DEBUG"))
+            fprintf(stderr, "libvc: hipGetDeviceCount -> %s, count %d, device %d\n",
+                    hipGetErrorString(he), count, device);
         return VC_EDEVICE;
-    if (hipSetDevice(device) != hipSuccess) return VC_EDEVICE;
+    }
+    he = hipSetDevice(device);
+    if (he != hipSuccess) {
+        if (getenv("VC_DEBUG"))
+            fprintf(stderr, "libvc: hipSetDevice -> %s\n", hipGetErrorString(he));
+        return VC_EDEVICE;
+    }
     vc_ctx* c = new (std::nothrow) vc_ctx();
     if (!c) return VC_ENOMEM;
     c->device = device;
     if (opts) c->opts = *opts;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    he = hipGetDeviceProperties(&prop, device);
+    if (he != hipSuccess) {
+        if (getenv("VC_DEBUG"))
+            fprintf(stderr, "libvc: hipGetDeviceProperties -> %s\n", hipGetErrorString(he));
         delete c;
         return VC_EDEVICE;
     }
@@ -472,14 +508,20 @@ vc_status vc_ctx_create(int device, void* stream, const vc_opts* opts, vc_ctx** 
     if (stream) {
         c->stream = (hipStream_t)stream;
     } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (he != hipSuccess) {
+            if (getenv("VC_DEBUG"))
+                fprintf(stderr, "libvc: hipStreamCreateWithFlags -> %s\n", hipGetErrorString(he));
             delete c;
             return VC_EDEVICE;
         }
         c->own_stream = true;
     }
     for (auto& e : c->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
+        he = hipEventCreate(&e);
+        if (he != hipSuccess) {
+            if (getenv("VC_DEBUG"))
+                fprintf(stderr, "libvc: hipEventCreate -> %s\n", hipGetErrorString(he));
             vc_ctx_destroy(c);
             return VC_EDEVICE;
         }

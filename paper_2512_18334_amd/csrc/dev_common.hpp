@@ -139,6 +139,23 @@ __device__ __forceinline__ bool cas_relaxed64(uint64_t* p, uint64_t expect, uint
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Coherent accesses for data that crosses workers (worklist payloads,
+// cover bitmaps): relaxed agent-scope atomic loads and stores, which compile
+// to global_load/store with the device-scope cache policy, so a reader on
+// another XCD never sees a stale cached copy.
+__device__ __forceinline__ void st_coh(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_coh(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void backoff(uint32_t& spins) {
     if (spins < 8) {
         __builtin_amdgcn_s_sleep(1);

@@ -18,8 +18,11 @@ struct SlotHdr {
     int32_t scope;     // registry entry of the scope (0 = the root)
     uint32_t branch_v; // NONE, or: first put N(branch_v) into the cover
     uint32_t nlive;    // live vertices when stored (diagnostic)
-    uint32_t pad[4];
+    uint32_t stamp;    // worklist position the slot was published for
+    uint32_t pad[3];
 };
+// A slot also ends with a 16-byte trailer whose first word repeats the
+// stamp: a consumer accepts the payload only when both stamps match.
 static_assert(sizeof(SlotHdr) == 32, "slot header is 32 bytes");
 
 // Component branch registry entry (Sec. III-C).  A child entry (a component,
@@ -59,7 +62,8 @@ struct Ctl {
     uint64_t components;
     uint64_t donations;
     uint64_t pushes;
-    uint64_t _p5[11];
+    uint64_t stale;   // worklist reads that saw an old payload and re-read
+    uint64_t _p5[10];
 };
 
 struct SearchArgs {

@@ -332,24 +332,41 @@ struct Worker {
 
     // ------------------------------------------------------- node I/O
 
-    __device__ void store_slot(uint8_t* slot, int ss, int sc, uint32_t bv) {
+    // Write a slot: header (stamp = worklist position, or 0 on the private
+    // stack), the degree array src (n_pad elements in LDS) and the trailer.
+    // Worklist slots (coh) are written with coherent stores; private stack
+    // slots are written and read by this worker only and use plain stores.
+    __device__ void write_slot(uint8_t* slot, int ss, int sc, uint32_t bv, uint32_t live,
+                               uint32_t stamp, const D* src, bool coh) {
         const uint32_t l = lane();
-        if (l == 0) {
-            SlotHdr h;
-            h.s = ss;
-            h.scope = sc;
-            h.branch_v = bv;
-            h.nlive = nl;
-            h.pad[0] = h.pad[1] = h.pad[2] = h.pad[3] = 0;
-            *reinterpret_cast<SlotHdr*>(slot) = h;
+        uint32_t hw = 0;  // header word l (8 words)
+        if (l == 0) hw = (uint32_t)ss;
+        if (l == 1) hw = (uint32_t)sc;
+        if (l == 2) hw = bv;
+        if (l == 3) hw = live;
+        if (l == 4) hw = stamp;
+        uint32_t* h = reinterpret_cast<uint32_t*>(slot);
+        uint32_t* tr = reinterpret_cast<uint32_t*>(slot + A.slot_bytes - 16u);
+        const uint32_t nw = (n_pad * (uint32_t)sizeof(D)) / 8u;
+        const uint64_t* s8 = reinterpret_cast<const uint64_t*>(src);
+        uint64_t* d8 = reinterpret_cast<uint64_t*>(slot + sizeof(SlotHdr));
+        if (coh) {
+            if (l < 8) st_coh(&h[l], hw);
+            if (l < 4) st_coh(&tr[l], l == 0 ? stamp : 0u);
+            for (uint32_t i = l; i < nw; i += 64) st_coh64(&d8[i], s8[i]);
+        } else {
+            if (l < 8) h[l] = hw;
+            if (l < 4) tr[l] = l == 0 ? stamp : 0u;
+            for (uint32_t i = l; i < nw; i += 64) d8[i] = s8[i];
         }
-        const uint4* src = reinterpret_cast<const uint4*>(deg);
-        uint4* dst = reinterpret_cast<uint4*>(slot + sizeof(SlotHdr));
-        const uint32_t nv = (n_pad * (uint32_t)sizeof(D)) / 16u;
-        for (uint32_t i = l; i < nv; i += 64) dst[i] = src[i];
     }
 
-    // copy a node into LDS; returns its pending branch vertex (or NONE)
+    __device__ void store_slot(uint8_t* slot, int ss, int sc, uint32_t bv, uint32_t stamp,
+                               bool coh) {
+        write_slot(slot, ss, sc, bv, nl, stamp, deg, coh);
+    }
+
+    // copy a private-stack node into LDS; returns its pending branch vertex
     __device__ uint32_t copy_slot(const uint8_t* slot) {
         const uint32_t l = lane();
         const SlotHdr h = *reinterpret_cast<const SlotHdr*>(slot);
@@ -362,6 +379,31 @@ struct Worker {
         uint32_t bv = uni(h.branch_v);
         wave_sync();
         return bv;
+    }
+
+    // copy a worklist node into LDS with coherent loads; returns the stamps
+    // (header, trailer) through st0/st1 and the pending branch vertex
+    __device__ uint32_t copy_slot_coh(const uint8_t* slot, uint32_t& st0, uint32_t& st1) {
+        const uint32_t l = lane();
+        const uint32_t* h = reinterpret_cast<const uint32_t*>(slot);
+        const uint32_t* tr = reinterpret_cast<const uint32_t*>(slot + A.slot_bytes - 16u);
+        uint32_t hw = l < 8 ? ld_coh(&h[l]) : 0u;
+        uint32_t t0 = l == 0 ? ld_coh(&tr[0]) : 0u;
+        const uint64_t* s8 = reinterpret_cast<const uint64_t*>(slot + sizeof(SlotHdr));
+        uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
+        const uint32_t nw = (n_pad * (uint32_t)sizeof(D)) / 8u;
+        for (uint32_t i = l; i < nw; i += 64) d8[i] = ld_coh64(&s8[i]);
+        s = (int)shfl(hw, 0);
+        scope = (int)shfl(hw, 1);
+        const uint32_t bv = shfl(hw, 2);
+        st0 = shfl(hw, 4);
+        st1 = shfl(t0, 0);
+        s = uni(s);
+        scope = uni(scope);
+        st0 = uni(st0);
+        st1 = uni(st1);
+        wave_sync();
+        return uni(bv);
     }
 
     // start on a node copied into LDS: live list, then the pending N(v)
@@ -465,7 +507,19 @@ struct Worker {
         res = uni(res);
         if (res == ~0ull) return false;
         wave_sync();
-        uint32_t bv = copy_slot(A.wl_slots + (size_t)(res % A.wl_cap) * A.slot_bytes);
+        const uint8_t* slot = A.wl_slots + (size_t)(res % A.wl_cap) * A.slot_bytes;
+        const uint32_t want = (uint32_t)res;
+        uint32_t s0 = 0, s1 = 0;
+        uint32_t bv = copy_slot_coh(slot, s0, s1);
+        for (uint32_t tries = 0; !(s0 == want && s1 == want) && tries < 100000; ++tries) {
+            // an old copy of the slot was read: count it and read again
+            if (lane() == 0) {
+                if (tries == 0) add_relaxed(&A.ctl->stale, 1ull);
+                fence_acquire();
+            }
+            wave_sync();
+            bv = copy_slot_coh(slot, s0, s1);
+        }
         if (lane() == 0) st_release(&A.wl_seq[res % A.wl_cap], res + A.wl_cap);
         begin_node(bv);
         return true;
@@ -479,19 +533,19 @@ struct Worker {
         if (hungry()) {
             uint64_t pos = wl_reserve();
             if (pos != ~0ull) {
-                fill(A.wl_slots + (size_t)(pos % A.wl_cap) * A.slot_bytes);
+                fill(A.wl_slots + (size_t)(pos % A.wl_cap) * A.slot_bytes, (uint32_t)pos, true);
                 wl_publish(pos);
                 return true;
             }
         }
         if (top < A.stack_depth) {
-            fill(stack + (size_t)top * A.slot_bytes);
+            fill(stack + (size_t)top * A.slot_bytes, 0u, false);
             ++top;
             return true;
         }
         uint64_t pos = wl_reserve();
         if (pos != ~0ull) {
-            fill(A.wl_slots + (size_t)(pos % A.wl_cap) * A.slot_bytes);
+            fill(A.wl_slots + (size_t)(pos % A.wl_cap) * A.slot_bytes, (uint32_t)pos, true);
             wl_publish(pos);
             return true;
         }
@@ -533,6 +587,20 @@ struct Worker {
 
     __device__ uint32_t* bitmap(int e) { return A.bitmaps + (size_t)e * A.bm_words; }
 
+    // registry entries are only ever accessed with atomics
+    __device__ void init_entry(int e, int best_or_sum, int live, int up, int cover_size,
+                               int nchild, int size) {
+        RegEntry* r = &A.reg[e];
+        st_relaxed(&r->best, best_or_sum);
+        st_relaxed(&r->live, live);
+        st_relaxed(&r->up, up);
+        st_relaxed(&r->lock, 0);
+        st_relaxed(&r->cover_size, cover_size);
+        st_relaxed(&r->nchild, nchild);
+        st_relaxed(&r->size, size);
+        st_relaxed(&r->pad, 0);
+    }
+
     // write the IN marks of the LDS degree array as bitmap words
     __device__ void write_in_bitmap(uint32_t* bm) {
         const uint32_t l = lane();
@@ -543,7 +611,7 @@ struct Worker {
                 uint32_t v = v0 + j;
                 if (v < n && DG::get(deg, v) == DG::IN) bits |= 1u << j;
             }
-            bm[wi] = bits;
+            st_coh(&bm[wi], bits);
         }
     }
 
@@ -565,9 +633,9 @@ struct Worker {
             } else {
                 const int nch = reg_field(&A.reg[from].nchild);
                 for (uint32_t wi = lane(); wi < A.bm_words; wi += 64) {
-                    uint32_t x = bitmap(from)[wi];
-                    for (int c = 1; c <= nch; ++c) x |= bitmap(from + c)[wi];
-                    dst[wi] = x;
+                    uint32_t x = ld_coh(&bitmap(from)[wi]);
+                    for (int c = 1; c <= nch; ++c) x |= ld_coh(&bitmap(from + c)[wi]);
+                    st_coh(&dst[wi], x);
                 }
             }
             wave_sync();
@@ -636,7 +704,10 @@ struct Worker {
         const uint32_t v = ~(uint32_t)(key & 0xFFFFFFFFull);
         if (scope != 0 && lane() == 0) add_relaxed(&A.reg[scope].live, 1);
         const int ss = s, sc = scope;
-        if (!push_node([&](uint8_t* slot) { store_slot(slot, ss, sc, v); })) return false;
+        if (!push_node([&](uint8_t* slot, uint32_t stamp, bool coh) {
+                store_slot(slot, ss, sc, v, stamp, coh);
+            }))
+            return false;
         if (lane() == 0) R[0] = v;
         wave_sync();
         take_list(R, 1);
@@ -692,11 +763,18 @@ struct Worker {
 
     // Branch on components (Alg. 2): one parent entry plus one child entry
     // per component, best_i = min(best - sum, |V_i| - 1); children other
-    // than the first are pushed, the first continues here.  Returns false
-    // when the registry is full (the caller then branches on a vertex).
-    __device__ bool component_branch(uint32_t nc, uint32_t nt) {
+    // than the first are pushed, the first continues here.  Returns CB_FULL
+    // when the registry is full (the caller then branches on a vertex) and
+    // CB_PRUNED when the scope's bound leaves no room for the components.
+    enum { CB_OK = 0, CB_FULL = 1, CB_PRUNED = 2 };
+    __device__ int component_branch(uint32_t nc, uint32_t nt) {
         const uint32_t l = lane();
         const uint32_t* NT = R + nc + 1;
+        // the bound may have improved since the node started: every
+        // component needs at least one vertex
+        const int bnow = scope_best(scope);
+        const int base_sum = s;
+        if ((int64_t)base_sum + nt >= (int64_t)bnow) return CB_PRUNED;
         uint32_t want = (nt + 1u + 3u) & ~3u;  // whole 128-byte lines
         uint32_t p = NONE;
         if (l == 0) {
@@ -712,22 +790,9 @@ struct Worker {
             }
         }
         p = uni(p);
-        if (p == NONE) return false;
-        const int bnow = scope_best(scope);
-        const int base_sum = s;
+        if (p == NONE) return CB_FULL;
         // parent entry: Sum = |S| (with the settled components), LiveComps
-        if (l == 0) {
-            RegEntry pe;
-            pe.best = base_sum;
-            pe.live = (int)nt;
-            pe.up = scope;
-            pe.lock = 0;
-            pe.cover_size = INF;
-            pe.nchild = (int)nt;
-            pe.size = 0;
-            pe.pad = 0;
-            A.reg[p] = pe;
-        }
+        if (l == 0) init_entry((int)p, base_sum, (int)nt, scope, INF, (int)nt, 0);
         write_in_bitmap(bitmap((int)p));
         // child entries and their initial covers (V_i minus one vertex)
         for (uint32_t j = 0; j < nt; ++j) {
@@ -739,18 +804,9 @@ struct Worker {
             uint32_t mx = 0;
             for (uint32_t i = a + l; i < b; i += 64) mx = Q[i] > mx ? Q[i] : mx;
             mx = wave_max(mx);
-            if (l == 0) {
-                RegEntry ce;
-                ce.best = bi;
-                ce.live = 1;
-                ce.up = (int)p;
-                ce.lock = 0;
-                ce.cover_size = attained ? (int)size - 1 : INF;
-                ce.nchild = 0;
-                ce.size = (int)size;
-                ce.pad = 0;
-                A.reg[p + 1 + j] = ce;
-            }
+            if (l == 0)
+                init_entry((int)(p + 1 + j), bi, 1, (int)p, attained ? (int)size - 1 : INF, 0,
+                           (int)size);
             if (attained) {
                 for (uint32_t i = l; i < bw; i += 64) VB[i] = 0u;
                 wave_sync();
@@ -760,7 +816,7 @@ struct Worker {
                 }
                 wave_sync();
                 uint32_t* bm = bitmap((int)(p + 1 + j));
-                for (uint32_t i = l; i < A.bm_words; i += 64) bm[i] = VB[i];
+                for (uint32_t i = l; i < A.bm_words; i += 64) st_coh(&bm[i], VB[i]);
             }
             wave_sync();
         }
@@ -775,27 +831,24 @@ struct Worker {
             const uint32_t c = NT[j];
             const uint32_t a = R[c], b = R[c + 1];
             const int sc = (int)(p + 1 + j);
-            bool ok = push_node([&](uint8_t* slot) {
-                if (l == 0) {
-                    SlotHdr h;
-                    h.s = 0;
-                    h.scope = sc;
-                    h.branch_v = NONE;
-                    h.nlive = b - a;
-                    h.pad[0] = h.pad[1] = h.pad[2] = h.pad[3] = 0;
-                    *reinterpret_cast<SlotHdr*>(slot) = h;
-                }
-                uint4* dst = reinterpret_cast<uint4*>(slot + sizeof(SlotHdr));
+            // the child's degree array: this component only, built in L
+            // (free until child 0 rebuilds it)
+            D* cd = reinterpret_cast<D*>(L);
+            {
+                uint4* z = reinterpret_cast<uint4*>(cd);
                 const uint32_t nv = (n_pad * (uint32_t)sizeof(D)) / 16u;
-                for (uint32_t i = l; i < nv; i += 64) dst[i] = make_uint4(0u, 0u, 0u, 0u);
+                for (uint32_t i = l; i < nv; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
                 wave_sync();
-                D* sd = reinterpret_cast<D*>(slot + sizeof(SlotHdr));
                 for (uint32_t i = a + l; i < b; i += 64) {
                     uint32_t v = Q[i];
-                    sd[v] = (D)DG::get(deg, v);
+                    cd[v] = (D)DG::get(deg, v);
                 }
+                wave_sync();
+            }
+            bool ok = push_node([&](uint8_t* slot, uint32_t stamp, bool coh) {
+                write_slot(slot, 0, sc, NONE, b - a, stamp, cd, coh);
             });
-            if (!ok) return true;  // error flagged; stop
+            if (!ok) return CB_OK;  // error flagged; the next node stops
         }
         // child 0 continues in LDS: keep only its component, S restarts
         {
@@ -816,7 +869,7 @@ struct Worker {
             build_live();
             known_connected = true;
         }
-        return true;
+        return CB_OK;
     }
 
     // Process one node and, depth-first, its first children in place.
@@ -861,7 +914,12 @@ struct Worker {
                     known_connected = true;
                     if (nt != nc) continue;  // re-run the rules on what is left
                 } else {
-                    if (component_branch(nc, nt)) continue;
+                    const int cb = component_branch(nc, nt);
+                    if (cb == CB_OK) continue;
+                    if (cb == CB_PRUNED) {
+                        complete(scope, false);
+                        return;
+                    }
                 }
             }
             if (!vertex_branch()) return;
@@ -952,6 +1010,8 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         h->scope = 0;
         h->branch_v = NONE;
         h->nlive = a.n;
+        h->stamp = 0;
+        *reinterpret_cast<uint32_t*>(a.wl_slots + a.slot_bytes - 16u) = 0u;
         Ctl* c = a.ctl;
         c->wl_head = 0;
         c->wl_tail = 1;
@@ -961,6 +1021,7 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         c->err = 0;
         c->reg_next = 4;  // entry 0 is the root scope; allocations are 4-aligned
         c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
+        c->stale = 0;
         RegEntry r;
         r.best = best0;
         r.live = 1;

@@ -74,6 +74,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it first "
                           "(python -m paper_2512_18334_amd.build)")
+    # libvc and PyTorch must share one HIP runtime: importing torch first
+    # loads its libamdhip64, which libvc then binds to (same soname)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     p = ctypes.c_void_p
     u32p = ctypes.POINTER(ctypes.c_uint32)
