@@ -85,6 +85,11 @@ typedef struct {
  *   watchdog_ms   a worker that has waited this long for work while work
  *                 is still outstanding stops the search with VC_EDEVICE
  *                 (default 120000).
+ *   donate_min    nodes with fewer live vertices are never donated (their
+ *                 subtrees are too small to pay for the move; default 64).
+ *   gcache_words  LDS graph cache per worker, in 32-bit words: components
+ *                 whose induced subgraph fits are re-induced with local ids
+ *                 (default: the most that still fits three workers per CU).
  */
 typedef struct {
     uint32_t workers;
@@ -95,6 +100,8 @@ typedef struct {
     uint64_t node_limit;
     uint32_t flags;
     uint32_t watchdog_ms;
+    uint32_t donate_min;
+    uint32_t gcache_words;
 } vc_opts;
 
 /* Statistics of the last completed solve on a context. */
@@ -105,6 +112,10 @@ typedef struct {
     uint64_t donations;          /* nodes handed to the shared worklist    */
     uint64_t pushes;             /* node slots written to HBM (stacks and
                                     worklist); each is read back once       */
+    uint64_t local_views;        /* components re-induced with local ids   */
+    uint64_t cycles[6];          /* shader cycles summed over workers:
+                                    fetch, rules, components, vertex branch,
+                                    registry completion, idle (Sec. V-D)    */
     uint32_t n_input;            /* vertices of the input graph             */
     uint32_t n_kernel;           /* vertices left after the root reduction  */
     uint64_t nnz_kernel;         /* CSR entries of the induced subgraph     */

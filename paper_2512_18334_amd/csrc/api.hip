@@ -64,7 +64,7 @@ struct vc_ctx {
     DevBuf rdeg, gdeg, gin, addf, newly, flags, newid, oldid, kdeg, koff, kcol, cover, scan_tmp,
         ctr, hsum;
     // search buffers
-    DevBuf stacks, wl_slots, wl_seq, ctl, reg, bitmaps;
+    DevBuf stacks, wl_slots, wl_seq, ctl, reg, bitmaps, arena;
     hipEvent_t ev[6] = {};
 };
 
@@ -315,7 +315,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         kbest = 0;
         improved = true;
     } else {
-        const uint32_t kcol_bytes = np <= 65536u ? 2u : 4u;
+        const uint32_t kcol_bytes = 4u;  // the search reads 32-bit column ids
         HIPCHK(root_induce_b(rg, b, np, kcol_bytes, s));
         uint32_t nz = 0;
         HIPCHK(hipMemcpyAsync(&nz, b.koff + np, 4, hipMemcpyDeviceToHost, s));
@@ -328,10 +328,24 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         const uint32_t deg_bytes = dmax <= 254u ? 1u : (dmax <= 65534u ? 2u : 4u);
         stv.deg_bytes = deg_bytes;
         const uint32_t n_pad = (np + 63u) & ~63u;
-        const LdsPlan lp = lds_plan(n_pad, deg_bytes);
+        // LDS graph cache: the caller's size, else the most that keeps three
+        // workers per CU (two, one as the graph grows), at most 16K words
+        const uint32_t base_lds = lds_plan(n_pad, deg_bytes, 0).bytes;
+        uint32_t gwords = c->opts.gcache_words;
+        if (!gwords) {
+            const uint32_t cu_lds = (uint32_t)(c->lds_max < 163840 ? c->lds_max : 163840);
+            for (uint32_t per = 3; per >= 1; --per) {
+                const uint32_t share = cu_lds / per;
+                if (share > base_lds + 4096u) {
+                    gwords = std::min<uint32_t>(16384u, (share - base_lds - 64u) / 4u);
+                    break;
+                }
+            }
+        }
+        const LdsPlan lp = lds_plan(n_pad, deg_bytes, gwords);
         if (lp.bytes > c->lds_max) return VC_ERANGE;
         int bpc = 0;
-        HIPCHK(search_occupancy(deg_bytes, kcol_bytes, lp.bytes, &bpc));
+        HIPCHK(search_occupancy(deg_bytes, lp.bytes, &bpc));
         if (bpc < 1) return VC_ERANGE;
         uint32_t workers = c->opts.workers ? c->opts.workers : (uint32_t)(bpc * c->cus);
         const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes + 16u;
@@ -358,12 +372,14 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         HIPCHK(ensure(c->ctl, sizeof(Ctl)));
         HIPCHK(ensure(c->reg, sizeof(RegEntry) * reg_cap));
         HIPCHK(ensure(c->bitmaps, 4ull * bm_words * reg_cap));
+        uint64_t arena_words = std::min<uint64_t>(budget / 16 / 4, 64ull << 20);
+        HIPCHK(ensure(c->arena, 4ull * arena_words));
 
         SearchArgs a{};
         a.n = np;
         a.n_pad = n_pad;
         a.off = b.koff;
-        a.col = b.kcol;
+        a.col = (const uint32_t*)b.kcol;
         a.slot_bytes = slot_bytes;
         a.stack_depth = depth;
         a.stacks = (uint8_t*)c->stacks.p;
@@ -380,8 +396,13 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         a.lds_R = lp.R;
         a.lds_VB = lp.VB;
         a.lds_PB = lp.PB;
-        a.lds_misc = lp.misc;
+        a.lds_G = lp.G;
         a.lds_bytes = lp.bytes;
+        a.gcache_words = gwords;
+        a.arena = (uint32_t*)c->arena.p;
+        a.arena_words = arena_words;
+        a.donate_min = c->opts.donate_min ? c->opts.donate_min : 64u;
+        a.strong_fences = getenv("VC_STRONG_FENCES") ? 1u : 0u;
         a.pvc = pvc;
         a.k = pvc ? (int)k - (int)sroot : 0;
         a.flags = c->opts.flags;
@@ -391,7 +412,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
 
         HIPCHK(launch_search_init(a, kbest0, deg_bytes, b.kdeg, s));
         HIPCHK(hipEventRecord(c->ev[3], s));
-        HIPCHK(launch_search(a, deg_bytes, kcol_bytes, workers, s));
+        HIPCHK(launch_search(a, deg_bytes, workers, s));
         HIPCHK(hipEventRecord(c->ev[4], s));
         Ctl ctl;
         RegEntry root;
@@ -403,6 +424,8 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         stv.components = ctl.components;
         stv.donations = ctl.donations;
         stv.pushes = ctl.pushes;
+        stv.local_views = ctl.local_views;
+        for (int i = 0; i < 6; ++i) stv.cycles[i] = ctl.cyc[i];
         stv.slot_bytes = slot_bytes;
         stv.bitmap_bytes = 4u * bm_words;
         float ms = 0;
@@ -420,13 +443,14 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         if (getenv("VC_DEBUG_REGISTRY")) {
             // after a complete MVC search every counter must be back at 0
             const uint32_t used = std::min<uint32_t>(ctl.reg_next, (uint32_t)reg_cap);
+            // entries whose parent and child counters are all back at zero
             std::vector<RegEntry> ents(used);
             HIPCHK(hipMemcpy(ents.data(), c->reg.p, sizeof(RegEntry) * used,
                              hipMemcpyDeviceToHost));
             uint32_t pos = 0, neg = 0, parents = 0;
-            for (uint32_t i = 4; i < used; ++i) {
+            for (uint32_t i = 2; i < used; ++i) {
                 const RegEntry& r = ents[i];
-                if (r.up < 0 && r.nchild == 0 && r.size == 0) continue;  // padding
+                if (r.up <= 0 && r.nchild == 0 && r.size == 0) continue;  // padding
                 if (r.nchild > 0) ++parents;
                 if (r.live > 0) ++pos;
                 if (r.live < 0) ++neg;
@@ -438,7 +462,8 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
                     root.cover_size, kbest0, ctl.done);
         }
         if (root.best < kbest0) {
-            if (root.cover_size != root.best) return VC_EDEVICE;  // internal invariant
+            // internal invariant: the root's bitmap holds a cover of size Best
+            if (root.cover_size != root.best) return VC_EDEVICE;
             improved = true;
             kbest = root.best;
             root_bitmap = (uint32_t*)c->bitmaps.p;
@@ -456,8 +481,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     uint32_t cnt = 0;
     HIPCHK(hipMemcpyAsync(&cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (cnt != size) return VC_EDEVICE;  // internal invariant: |cover| == size
-    out->size = size;
+    // internal invariant: |cover| == size (MVC); in PVC a cover assembled
+    // while components were still improving may be smaller than its bound
+    if (pvc ? cnt > size : cnt != size) return VC_EDEVICE;
+    out->size = pvc ? cnt : size;
     out->yes = pvc ? (size <= k) : 1;
     out->cover_count = cnt;
     st = fetch_cover(c, b, cnt, cover, cover_len);
@@ -537,7 +564,7 @@ vc_status vc_ctx_destroy(vc_ctx* c) {
     DevBuf* bufs[] = {&c->in_off, &c->in_col, &c->rdeg, &c->gdeg, &c->gin, &c->addf,
                       &c->newly, &c->flags, &c->newid, &c->oldid, &c->kdeg, &c->koff,
                       &c->kcol, &c->cover, &c->scan_tmp, &c->ctr, &c->hsum, &c->stacks,
-                      &c->wl_slots, &c->wl_seq, &c->ctl, &c->reg, &c->bitmaps};
+                      &c->wl_slots, &c->wl_seq, &c->ctl, &c->reg, &c->bitmaps, &c->arena};
     for (DevBuf* b : bufs)
         if (b->p) hipFree(b->p);
     for (auto& e : c->ev)

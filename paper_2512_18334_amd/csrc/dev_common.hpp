@@ -156,11 +156,20 @@ __device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Wait until every memory operation this wave issued has completed.  With
+// all cross-worker data moved by coherent accesses, this is the ordering
+// point between writing a payload and publishing it (and between the two
+// halves of a registry update), without the whole-cache write-back and
+// invalidate an agent-scope fence costs on a multi-XCD part.
+__device__ __forceinline__ void order_point() { __builtin_amdgcn_s_waitcnt(0); }
+
+// idle wait: short sleeps first, then up to 8 x 63 x 64 clocks per round
 __device__ __forceinline__ void backoff(uint32_t& spins) {
-    if (spins < 8) {
-        __builtin_amdgcn_s_sleep(1);
+    if (spins < 4) {
+        __builtin_amdgcn_s_sleep(2);
     } else {
-        __builtin_amdgcn_s_sleep(16);
+        const uint32_t reps = spins < 12 ? 1u : (spins < 24 ? 4u : 8u);
+        for (uint32_t i = 0; i < reps; ++i) __builtin_amdgcn_s_sleep(63);
     }
     ++spins;
 }

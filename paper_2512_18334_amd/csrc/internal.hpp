@@ -10,19 +10,20 @@ constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int INF = 0x3FFFFFFF;
 
 // Search-node slot in HBM (private stacks and the shared worklist): this
-// 32-byte header followed by the degree array (n_pad elements of the degree
-// type).  The degree array is the node's whole state (Sec. IV-A): entry 0 =
-// no remaining edge, all-ones = in the cover, else the live degree.
+// 32-byte header, the degree array of the node's graph view (entry 0 = no
+// remaining edge, all-ones = in the cover, else the live degree; Sec. IV-A),
+// and at the end of the slot a 16-byte trailer whose first word repeats the
+// stamp.  Slots have room for the largest view; a node moves only the part
+// its view needs.
 struct SlotHdr {
     int32_t s;         // |S| counted in the node's scope
     int32_t scope;     // registry entry of the scope (0 = the root)
     uint32_t branch_v; // NONE, or: first put N(branch_v) into the cover
     uint32_t nlive;    // live vertices when stored (diagnostic)
-    uint32_t stamp;    // worklist position the slot was published for
-    uint32_t pad[3];
+    uint32_t stamp;    // worklist position the slot was published for (0 on stacks)
+    int32_t view;      // registry entry whose graph the degree array indexes
+    uint32_t pad[2];
 };
-// A slot also ends with a 16-byte trailer whose first word repeats the
-// stamp: a consumer accepts the payload only when both stamps match.
 static_assert(sizeof(SlotHdr) == 32, "slot header is 32 bytes");
 
 // Component branch registry entry (Sec. III-C).  A child entry (a component,
@@ -30,7 +31,14 @@ static_assert(sizeof(SlotHdr) == 32, "slot header is 32 bytes");
 // entry (a node that branched on components) holds {Sum, LiveComps,
 // AncestorIdx}.  Entries of one branch are contiguous: parent p, then its
 // children p+1 .. p+nchild.  Every entry owns one cover bitmap: a child's
-// best cover found so far, a parent's vertices taken before the split.
+// best cover found so far, a parent's vertices taken before the split, both
+// in the ids of the entry's graph view.
+//
+// Graph views: a small component gets its own induced subgraph with local
+// ids 0..size-1 (CSR plus the map back to the ids of the view it was cut
+// from) in the graph arena; its entry is then its own view.  Otherwise it
+// keeps the view of the scope it was found in.  The root's view is the
+// subgraph induced after the root reduction.
 struct RegEntry {
     int best;       // child: Best          | parent: Sum
     int live;       // child: LiveNodes     | parent: LiveComps
@@ -39,9 +47,15 @@ struct RegEntry {
     int cover_size; // vertices in the bitmap (INF: no attained cover yet)
     int nchild;     // parent: number of children
     int size;       // child: vertices of the component
-    int pad;
+    int view;       // child/root: entry whose graph ids the scope uses
+    int vn;         // child/root: vertex count of that view
+    uint32_t g_at;  // own view: word offset in the arena of off[vn+1], col[nnz], l2g[vn]
+    int g_nnz;      // own view: CSR entries
+    int att;        // parent, PVC: Sum plus the children's attained covers
+    int unatt;      // parent, PVC: children without an attained cover yet
+    int pad[3];
 };
-static_assert(sizeof(RegEntry) == 32, "registry entry is 32 bytes");
+static_assert(sizeof(RegEntry) == 64, "registry entry is 64 bytes");
 
 // Control block (one per solve), fields on separate 128-byte lines.
 struct Ctl {
@@ -57,20 +71,29 @@ struct Ctl {
     int err;          // vc_status of a device-side failure
     uint32_t reg_next;
     int _p4[29];
+    uint64_t arena_next;  // words of the graph arena in use
+    uint64_t _p6[15];
     uint64_t nodes;   // statistics
     uint64_t comp_branches;
     uint64_t components;
     uint64_t donations;
     uint64_t pushes;
     uint64_t stale;   // worklist reads that saw an old payload and re-read
-    uint64_t _p5[10];
+    uint64_t local_views;  // components given their own induced subgraph
+    uint64_t _p5[9];
+    // shader cycles summed over workers, by activity (the time breakdown
+    // of Sec. V-D): fetching nodes, rules, component search and
+    // registration, vertex branching, registry completion, waiting for work
+    uint64_t cyc[6];
+    uint64_t _p7[10];
 };
+enum { CYC_FETCH = 0, CYC_REDUCE, CYC_COMPONENTS, CYC_BRANCH, CYC_COMPLETE, CYC_IDLE };
 
 struct SearchArgs {
-    uint32_t n;           // vertices of the induced subgraph
-    uint32_t n_pad;       // degree array elements (multiple of 64)
+    uint32_t n;           // vertices of the induced subgraph (root view)
+    uint32_t n_pad;       // largest degree array (multiple of 64)
     const uint32_t* off;  // CSR of the induced subgraph
-    const void* col;
+    const uint32_t* col;
     uint32_t slot_bytes;
     uint32_t stack_depth;
     uint8_t* stacks;      // [workers][stack_depth][slot_bytes]
@@ -82,20 +105,26 @@ struct SearchArgs {
     RegEntry* reg;
     uint32_t* bitmaps;    // [reg_cap][bm_words]
     uint32_t bm_words;
-    uint32_t lds_L, lds_Q, lds_R, lds_VB, lds_PB, lds_misc, lds_bytes;
+    uint32_t* arena;      // graph arena (local views)
+    uint64_t arena_words;
+    uint32_t gcache_words;  // LDS graph cache capacity (words)
+    uint32_t lds_L, lds_Q, lds_R, lds_VB, lds_PB, lds_G, lds_bytes;
     int pvc;              // 1: parameterized (stop once the root is <= k)
     int k;
     uint32_t flags;       // VC_OPT_* ablation switches
     uint32_t donate_slack;
+    uint32_t donate_min;  // donate only nodes with at least this many live vertices
+    uint32_t strong_fences;  // 1: agent-scope release/acquire fences as well
     uint64_t node_limit;  // 0: none
     uint64_t watchdog_ticks;  // idle wait limit in wall_clock64() ticks
 };
 
-// LDS layout of one worker for n vertices and degree element size sd.
+// LDS layout of one worker: degree array, live list L, scratch lists Q and
+// R (R doubles as an id map of n_pad words), two bitmaps, graph cache.
 struct LdsPlan {
-    uint32_t L, Q, R, VB, PB, misc, bytes;
+    uint32_t L, Q, R, VB, PB, G, bytes;
 };
-inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd) {
+inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd, uint32_t gcache_words) {
     LdsPlan p;
     uint32_t at = n_pad * sd;
     at = (at + 15u) & ~15u;
@@ -105,7 +134,7 @@ inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd) {
     uint32_t bw = (n_pad + 31u) / 32u;
     p.VB = at; at += 4u * bw;
     p.PB = at; at += 4u * bw;
-    p.misc = at; at += 4u * 64u;
+    p.G = at; at += 4u * gcache_words;
     p.bytes = (at + 15u) & ~15u;
     return p;
 }
@@ -113,10 +142,9 @@ inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd) {
 // ------------------------------------------------------ kernel launchers
 // (defined in the .hip files; all launch on `st`)
 
-hipError_t launch_search(const SearchArgs& a, uint32_t deg_bytes, uint32_t col_bytes,
-                         uint32_t workers, hipStream_t st);
-hipError_t search_occupancy(uint32_t deg_bytes, uint32_t col_bytes, uint32_t lds_bytes,
-                            int* blocks_per_cu);
+hipError_t launch_search(const SearchArgs& a, uint32_t deg_bytes, uint32_t workers,
+                         hipStream_t st);
+hipError_t search_occupancy(uint32_t deg_bytes, uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_search_init(const SearchArgs& a, int best0, uint32_t deg_bytes,
                               const uint32_t* kdeg, hipStream_t st);
 

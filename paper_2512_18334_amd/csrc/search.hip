@@ -1,16 +1,25 @@
 // search.hip -- the persistent component-aware branch-and-reduce search.
 //
-// One 64-lane wave is one worker (Sec. II-C: prior work uses thread blocks;
-// on gfx950 a wave64 needs no block barriers and many more workers fit).
-// Each worker keeps the node it is solving in LDS: the degree array (in the
-// narrow type chosen after the root reduction, Sec. IV-D) plus a compacted
-// list of the live vertices (ballot/mbcnt compaction instead of the paper's
-// [lo, hi] window, Sec. IV-C), so rules, stopping tests and the component
-// search touch live vertices only.  Pending nodes go to the worker's private
-// stack in HBM or, when other workers are idle, to a shared bounded MPMC
-// worklist (Sec. II-C).  Branches on components (Alg. 2) are registered in a
-// registry in HBM; the last descendant to finish does the post-processing
-// (Sec. III-C).
+// One 64-lane wave is one worker (prior GPU work uses thread blocks, Sec.
+// II-C; on gfx950 a wave64 needs no block barriers and many more workers
+// fit).  A worker keeps the node it is solving in LDS: the degree array in
+// the narrow type chosen after the root reduction (Sec. IV-D) plus a
+// compacted list of live vertices (ballot/mbcnt compaction in place of the
+// paper's [lo, hi] window, Sec. IV-C), so rules, stopping tests and the
+// component search touch live vertices only.  Pending nodes go to the
+// worker's private stack in HBM or, while other workers are idle, to a
+// shared bounded MPMC worklist (Sec. II-C).  Branches on components (Alg. 2)
+// are registered in a registry in HBM whose last descendant does the
+// post-processing (Sec. III-C).  A small component is also re-induced as a
+// subgraph of its own with local ids (the paper's reduce-then-induce step,
+// Sec. IV-B, applied again at every branch on components), held in an LDS
+// graph cache while a worker is in its scope, so per-node work scales with
+// the component, not with the whole graph.
+//
+// Memory model: data that crosses workers (worklist slots, cover bitmaps,
+// registry entries, arena graphs) is only written and read with coherent
+// (device-scope) accesses, and s_waitcnt ordering points separate writing
+// a payload from publishing it; private stacks use plain accesses.
 #include "dev_common.hpp"
 #include "internal.hpp"
 #include "vc.h"
@@ -33,8 +42,8 @@ __device__ __forceinline__ uint64_t uni(uint64_t x) {
 // chunk of the flattened rows finds its row by a binary search over the
 // lanes' exclusive prefix sums (load-balanced expansion).  f(ok, v, w) is
 // called by all lanes in lock-step; ok is false on padding lanes.
-template <typename C, typename F>
-__device__ __forceinline__ void for_rows(const uint32_t* off, const C* col,
+template <typename F>
+__device__ __forceinline__ void for_rows(const uint32_t* off, const uint32_t* col,
                                          const uint32_t* list, uint32_t cnt, F&& f) {
     const uint32_t l = lane();
     for (uint32_t base = 0; base < cnt; base += 64) {
@@ -60,21 +69,23 @@ __device__ __forceinline__ void for_rows(const uint32_t* off, const C* col,
             uint32_t vj = shfl(v, j);
             uint32_t e = shfl(r0, j) + (t - shfl(excl, j));
             bool ok = t < total;
-            uint32_t w = ok ? (uint32_t)col[e] : 0u;
+            uint32_t w = ok ? col[e] : 0u;
             f(ok, vj, w);
         }
     }
 }
 
-template <typename D, typename C>
+template <typename D>
 struct Worker {
     using DG = Deg<D>;
-    const SearchArgs& A;
+    SearchArgs A;
     D* deg;
-    uint32_t *L, *Q, *R, *VB, *PB, *misc;
-    const uint32_t* off;
-    const C* col;
-    uint32_t n, n_pad, bw;
+    uint32_t *L, *Q, *R, *VB, *PB, *G;
+    // current graph view
+    int view;
+    uint32_t vn, vpad, vbw;
+    const uint32_t* voff;
+    const uint32_t* vcol;
     // node state (wave-uniform)
     uint32_t nl;    // live vertices in L
     int s;          // |S| in scope
@@ -85,8 +96,11 @@ struct Worker {
     bool known_connected;
     // worker state
     uint8_t* stack;
-    uint32_t top;
-    uint64_t nodes, cbr, comps, dons, pushes, nodes_flushed;
+    uint32_t bot, top;  // private stack as a deque: pop at top, donate from bot
+    uint32_t since_check;
+    uint64_t nodes, cbr, comps, dons, pushes, lviews, nodes_flushed;
+    uint64_t cyc[6];
+    uint64_t t_mark;
 
     __device__ Worker(const SearchArgs& a, uint8_t* lds) : A(a) {
         deg = reinterpret_cast<D*>(lds);
@@ -95,28 +109,92 @@ struct Worker {
         R = reinterpret_cast<uint32_t*>(lds + a.lds_R);
         VB = reinterpret_cast<uint32_t*>(lds + a.lds_VB);
         PB = reinterpret_cast<uint32_t*>(lds + a.lds_PB);
-        misc = reinterpret_cast<uint32_t*>(lds + a.lds_misc);
-        off = a.off;
-        col = reinterpret_cast<const C*>(a.col);
-        n = a.n;
-        n_pad = a.n_pad;
-        bw = (n_pad + 31u) / 32u;
+        G = reinterpret_cast<uint32_t*>(lds + a.lds_G);
         stack = a.stacks + (size_t)blockIdx.x * a.stack_depth * a.slot_bytes;
-        top = 0;
-        nodes = cbr = comps = dons = pushes = nodes_flushed = 0;
+        bot = top = 0;
+        for (int i = 0; i < 6; ++i) cyc[i] = 0;
+        t_mark = clock64();
+        since_check = 0;
+        nodes = cbr = comps = dons = pushes = lviews = nodes_flushed = 0;
         known_connected = false;
+        view = -1;
+        vn = vpad = vbw = 0;
+        voff = vcol = nullptr;
+    }
+
+    // charge the shader cycles since the last mark to activity k
+    __device__ __forceinline__ void charge(int k) {
+        const uint64_t t = clock64();
+        cyc[k] += t - t_mark;
+        t_mark = t;
+    }
+
+    // ------------------------------------------------------- registry access
+
+    __device__ int reg_field(const int* p) {
+        int b = 0;
+        if (lane() == 0) b = ld_relaxed(p);
+        return uni(b);
+    }
+    __device__ int scope_best(int e) { return reg_field(&A.reg[e].best); }
+    __device__ uint32_t* bitmap(int e) { return A.bitmaps + (size_t)e * A.bm_words; }
+
+    // registry entries are only ever accessed with coherent atomics
+    __device__ void init_entry(int e, int best_or_sum, int live, int up, int cover_size,
+                               int nchild, int size, int v, int vnn, uint32_t g_at, int g_nnz) {
+        RegEntry* r = &A.reg[e];
+        st_relaxed(&r->best, best_or_sum);
+        st_relaxed(&r->live, live);
+        st_relaxed(&r->up, up);
+        st_relaxed(&r->lock, 0);
+        st_relaxed(&r->cover_size, cover_size);
+        st_relaxed(&r->nchild, nchild);
+        st_relaxed(&r->size, size);
+        st_relaxed(&r->view, v);
+        st_relaxed(&r->vn, vnn);
+        st_relaxed(reinterpret_cast<int*>(&r->g_at), (int)g_at);
+        st_relaxed(&r->g_nnz, g_nnz);
+        st_relaxed(&r->att, 0);
+        st_relaxed(&r->unatt, 0);
+    }
+
+    // ------------------------------------------------------- graph views
+
+    // Make entry v's graph the current view: the root's induced subgraph is
+    // read from HBM directly; a component's own subgraph is copied from the
+    // arena into the LDS graph cache.
+    __device__ void load_view(int v) {
+        if (v == view) return;
+        if (v == 0) {
+            voff = A.off;
+            vcol = A.col;
+            vn = A.n;
+        } else {
+            const uint32_t g_at = (uint32_t)reg_field(reinterpret_cast<const int*>(&A.reg[v].g_at));
+            const uint32_t n = (uint32_t)reg_field(&A.reg[v].vn);
+            const uint32_t nnz = (uint32_t)reg_field(&A.reg[v].g_nnz);
+            const uint32_t* src = A.arena + g_at;
+            const uint32_t words = n + 1u + nnz;
+            for (uint32_t i = lane(); i < words; i += 64) G[i] = ld_coh(&src[i]);
+            wave_sync();
+            voff = G;
+            vcol = G + n + 1;
+            vn = n;
+        }
+        vpad = (vn + 63u) & ~63u;
+        vbw = vpad / 32u;
+        view = v;
     }
 
     // ------------------------------------------------------- live list
 
-    // rebuild L from the whole degree array
     __device__ void build_live() {
         const uint32_t l = lane();
         uint32_t cnt = 0;
         uint64_t sum = 0, k = 0;
-        for (uint32_t base = 0; base < n; base += 64) {
+        for (uint32_t base = 0; base < vn; base += 64) {
             uint32_t v = base + l;
-            uint32_t d = v < n ? DG::get(deg, v) : 0u;
+            uint32_t d = v < vn ? DG::get(deg, v) : 0u;
             bool lv = DG::live(d);
             uint64_t m = ballot(lv);
             if (lv) {
@@ -133,7 +211,6 @@ struct Worker {
         wave_sync();
     }
 
-    // drop vertices that left the graph from L (in place), refresh e2 / key
     __device__ void recompact() {
         const uint32_t l = lane();
         uint32_t cnt = 0;
@@ -172,7 +249,7 @@ struct Worker {
             nn += popc(m);
         }
         wave_sync();
-        for_rows(off, col, list, nn, [&](bool ok, uint32_t, uint32_t w) {
+        for_rows(voff, vcol, list, nn, [&](bool ok, uint32_t, uint32_t w) {
             if (ok && DG::live(DG::get(deg, w))) DG::dec(deg, w);
         });
         wave_sync();
@@ -184,10 +261,12 @@ struct Worker {
 
     __device__ bool adjacent(uint32_t u, uint32_t w) {
         uint32_t a = u, b = w;
-        uint32_t la = off[a + 1] - off[a], lb = off[b + 1] - off[b];
-        if (lb < la) { a = w; b = u; }
-        for (uint32_t e = off[a]; e < off[a + 1]; ++e)
-            if ((uint32_t)col[e] == b) return true;
+        if (voff[w + 1] - voff[w] < voff[u + 1] - voff[u]) {
+            a = w;
+            b = u;
+        }
+        for (uint32_t e = voff[a]; e < voff[a + 1]; ++e)
+            if (vcol[e] == b) return true;
         return false;
     }
 
@@ -230,8 +309,8 @@ struct Worker {
                 bool add_u = false, add_w = false;
                 if (d == 1u || d == 2u) {
                     uint32_t got = 0;
-                    for (uint32_t e = off[v]; e < off[v + 1] && got < d; ++e) {
-                        uint32_t x = (uint32_t)col[e];
+                    for (uint32_t e = voff[v]; e < voff[v + 1] && got < d; ++e) {
+                        uint32_t x = vcol[e];
                         if (DG::live(DG::get(deg, x))) {
                             if (got == 0) u = x; else w = x;
                             ++got;
@@ -275,7 +354,7 @@ struct Worker {
     // parity of each vertex's BFS level.  Returns nc.
     __device__ uint32_t find_components() {
         const uint32_t l = lane();
-        for (uint32_t i = l; i < bw; i += 64) {
+        for (uint32_t i = l; i < vbw; i += 64) {
             VB[i] = 0u;
             PB[i] = 0u;
         }
@@ -306,7 +385,7 @@ struct Worker {
             uint32_t fa = qn - 1, fb = qn, level = 0;
             while (fa < fb) {
                 const bool odd = ((level + 1u) & 1u) != 0u;
-                for_rows(off, col, Q + fa, fb - fa, [&](bool ok, uint32_t, uint32_t w) {
+                for_rows(voff, vcol, Q + fa, fb - fa, [&](bool ok, uint32_t, uint32_t w) {
                     bool nw = false;
                     if (ok && DG::live(DG::get(deg, w))) {
                         uint32_t bit = 1u << (w & 31u);
@@ -332,12 +411,11 @@ struct Worker {
 
     // ------------------------------------------------------- node I/O
 
-    // Write a slot: header (stamp = worklist position, or 0 on the private
-    // stack), the degree array src (n_pad elements in LDS) and the trailer.
-    // Worklist slots (coh) are written with coherent stores; private stack
+    // Write a slot: header, degree array src (npad elements of view vw) and
+    // trailer.  Worklist slots (coh) use coherent stores; private stack
     // slots are written and read by this worker only and use plain stores.
     __device__ void write_slot(uint8_t* slot, int ss, int sc, uint32_t bv, uint32_t live,
-                               uint32_t stamp, const D* src, bool coh) {
+                               uint32_t stamp, const D* src, int vw, uint32_t npad, bool coh) {
         const uint32_t l = lane();
         uint32_t hw = 0;  // header word l (8 words)
         if (l == 0) hw = (uint32_t)ss;
@@ -345,9 +423,10 @@ struct Worker {
         if (l == 2) hw = bv;
         if (l == 3) hw = live;
         if (l == 4) hw = stamp;
+        if (l == 5) hw = (uint32_t)vw;
         uint32_t* h = reinterpret_cast<uint32_t*>(slot);
         uint32_t* tr = reinterpret_cast<uint32_t*>(slot + A.slot_bytes - 16u);
-        const uint32_t nw = (n_pad * (uint32_t)sizeof(D)) / 8u;
+        const uint32_t nw = (npad * (uint32_t)sizeof(D)) / 8u;
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(src);
         uint64_t* d8 = reinterpret_cast<uint64_t*>(slot + sizeof(SlotHdr));
         if (coh) {
@@ -361,22 +440,19 @@ struct Worker {
         }
     }
 
-    __device__ void store_slot(uint8_t* slot, int ss, int sc, uint32_t bv, uint32_t stamp,
-                               bool coh) {
-        write_slot(slot, ss, sc, bv, nl, stamp, deg, coh);
-    }
-
     // copy a private-stack node into LDS; returns its pending branch vertex
     __device__ uint32_t copy_slot(const uint8_t* slot) {
         const uint32_t l = lane();
-        const SlotHdr h = *reinterpret_cast<const SlotHdr*>(slot);
-        const uint4* src = reinterpret_cast<const uint4*>(slot + sizeof(SlotHdr));
-        uint4* dst = reinterpret_cast<uint4*>(deg);
-        const uint32_t nv = (n_pad * (uint32_t)sizeof(D)) / 16u;
-        for (uint32_t i = l; i < nv; i += 64) dst[i] = src[i];
-        s = uni(h.s);
-        scope = uni(h.scope);
-        uint32_t bv = uni(h.branch_v);
+        const uint32_t* h = reinterpret_cast<const uint32_t*>(slot);
+        uint32_t hw = l < 8 ? h[l] : 0u;
+        s = uni((int)shfl(hw, 0));
+        scope = uni((int)shfl(hw, 1));
+        const uint32_t bv = uni(shfl(hw, 2));
+        load_view(uni((int)shfl(hw, 5)));
+        const uint64_t* s8 = reinterpret_cast<const uint64_t*>(slot + sizeof(SlotHdr));
+        uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
+        const uint32_t nw = (vpad * (uint32_t)sizeof(D)) / 8u;
+        for (uint32_t i = l; i < nw; i += 64) d8[i] = s8[i];
         wave_sync();
         return bv;
     }
@@ -389,21 +465,18 @@ struct Worker {
         const uint32_t* tr = reinterpret_cast<const uint32_t*>(slot + A.slot_bytes - 16u);
         uint32_t hw = l < 8 ? ld_coh(&h[l]) : 0u;
         uint32_t t0 = l == 0 ? ld_coh(&tr[0]) : 0u;
+        s = uni((int)shfl(hw, 0));
+        scope = uni((int)shfl(hw, 1));
+        const uint32_t bv = uni(shfl(hw, 2));
+        st0 = uni(shfl(hw, 4));
+        st1 = uni(shfl(t0, 0));
+        load_view(uni((int)shfl(hw, 5)));
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(slot + sizeof(SlotHdr));
         uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
-        const uint32_t nw = (n_pad * (uint32_t)sizeof(D)) / 8u;
+        const uint32_t nw = (vpad * (uint32_t)sizeof(D)) / 8u;
         for (uint32_t i = l; i < nw; i += 64) d8[i] = ld_coh64(&s8[i]);
-        s = (int)shfl(hw, 0);
-        scope = (int)shfl(hw, 1);
-        const uint32_t bv = shfl(hw, 2);
-        st0 = shfl(hw, 4);
-        st1 = shfl(t0, 0);
-        s = uni(s);
-        scope = uni(scope);
-        st0 = uni(st0);
-        st1 = uni(st1);
         wave_sync();
-        return uni(bv);
+        return bv;
     }
 
     // start on a node copied into LDS: live list, then the pending N(v)
@@ -417,10 +490,10 @@ struct Worker {
     __device__ void take_neighbours(uint32_t v) {
         const uint32_t l = lane();
         uint32_t cnt = 0;
-        const uint32_t r0 = off[v], r1 = off[v + 1];
+        const uint32_t r0 = voff[v], r1 = voff[v + 1];
         for (uint32_t e0 = r0; e0 < r1; e0 += 64) {
             uint32_t e = e0 + l;
-            uint32_t w = e < r1 ? (uint32_t)col[e] : 0u;
+            uint32_t w = e < r1 ? vcol[e] : 0u;
             bool lv = e < r1 && DG::live(DG::get(deg, w));
             uint64_t m = ballot(lv);
             if (lv) R[cnt + mbcnt(m)] = w;
@@ -433,8 +506,14 @@ struct Worker {
 
     // ------------------------------------------------------- worklist
 
-    __device__ bool hungry() {
+    __device__ void publish_order() {
+        if (A.strong_fences) fence_release();
+        order_point();
+    }
+
+    __device__ bool hungry(uint32_t live) {
         if (A.flags & VC_OPT_NO_LOAD_BALANCE) return false;
+        if (live < A.donate_min) return false;
         int idle = 0;
         uint64_t h = 0, t = 0;
         if (lane() == 0) {
@@ -444,7 +523,7 @@ struct Worker {
         }
         idle = uni(idle);
         uint64_t q = uni(t) - uni(h);
-        return (uint64_t)idle > q + A.donate_slack;
+        return idle > 0 && (uint64_t)idle > q + A.donate_slack;
     }
 
     // reserve a worklist position (UINT64_MAX when full)
@@ -476,7 +555,9 @@ struct Worker {
         wave_sync();
         if (lane() == 0) {
             add_relaxed(&A.ctl->outstanding, 1);
-            st_release(&A.wl_seq[pos % A.wl_cap], pos + 1);
+            publish_order();
+            __hip_atomic_store(&A.wl_seq[pos % A.wl_cap], pos + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
         ++dons;
     }
@@ -492,7 +573,7 @@ struct Worker {
                 int64_t diff = (int64_t)(seq - (pos + 1));
                 if (diff == 0) {
                     if (cas_relaxed64(&A.ctl->wl_head, pos, pos + 1)) {
-                        fence_acquire();
+                        if (A.strong_fences) fence_acquire();
                         res = pos;
                         break;
                     }
@@ -520,22 +601,35 @@ struct Worker {
             wave_sync();
             bv = copy_slot_coh(slot, s0, s1);
         }
-        if (lane() == 0) st_release(&A.wl_seq[res % A.wl_cap], res + A.wl_cap);
+        if (lane() == 0) {
+            order_point();
+            __hip_atomic_store(&A.wl_seq[res % A.wl_cap], res + A.wl_cap, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
         begin_node(bv);
         return true;
     }
 
-    // Place a pending node: the shared worklist when others are idle, else
-    // the own stack; the caller fills the slot through fill(slot).
+    // Place a pending node with `live` live vertices: the shared worklist
+    // when others are idle, else the own stack; fill(slot, stamp, coherent)
+    // writes it.
     template <typename Fill>
-    __device__ bool push_node(Fill&& fill) {
+    __device__ bool push_node(uint32_t live, Fill&& fill) {
         ++pushes;
-        if (hungry()) {
+        if (hungry(live)) {
+            // give away the oldest pending node (it roots the largest subtree)
+            // when there is one, else this one
             uint64_t pos = wl_reserve();
             if (pos != ~0ull) {
-                fill(A.wl_slots + (size_t)(pos % A.wl_cap) * A.slot_bytes, (uint32_t)pos, true);
-                wl_publish(pos);
-                return true;
+                uint8_t* dst = A.wl_slots + (size_t)(pos % A.wl_cap) * A.slot_bytes;
+                if (top > bot) {
+                    donate_bottom(dst, (uint32_t)pos);
+                    wl_publish(pos);
+                } else {
+                    fill(dst, (uint32_t)pos, true);
+                    wl_publish(pos);
+                    return true;
+                }
             }
         }
         if (top < A.stack_depth) {
@@ -553,6 +647,29 @@ struct Worker {
         return false;
     }
 
+    // move the bottom entry of the private stack into worklist slot dst
+    __device__ void donate_bottom(uint8_t* dst, uint32_t stamp) {
+        const uint32_t l = lane();
+        const uint8_t* src = stack + (size_t)bot * A.slot_bytes;
+        const uint32_t* h = reinterpret_cast<const uint32_t*>(src);
+        uint32_t hw = l < 8 ? h[l] : 0u;
+        if (l == 4) hw = stamp;
+        const uint32_t vw = uni(shfl(hw, 5));
+        // the entry's view decides how much of the degree array is in use
+        const uint32_t n = vw == 0u ? A.n : (uint32_t)reg_field(&A.reg[vw].vn);
+        const uint32_t npad = (n + 63u) & ~63u;
+        const uint32_t nw = (npad * (uint32_t)sizeof(D)) / 8u;
+        uint32_t* dh = reinterpret_cast<uint32_t*>(dst);
+        uint32_t* tr = reinterpret_cast<uint32_t*>(dst + A.slot_bytes - 16u);
+        if (l < 8) st_coh(&dh[l], hw);
+        if (l < 4) st_coh(&tr[l], l == 0 ? stamp : 0u);
+        const uint64_t* s8 = reinterpret_cast<const uint64_t*>(src + sizeof(SlotHdr));
+        uint64_t* d8 = reinterpret_cast<uint64_t*>(dst + sizeof(SlotHdr));
+        for (uint32_t i = l; i < nw; i += 64) st_coh64(&d8[i], s8[i]);
+        ++bot;
+        if (bot == top) bot = top = 0;
+    }
+
     __device__ void fail(int code) {
         if (lane() == 0) {
             atomicCAS(&A.ctl->err, 0, code);
@@ -560,18 +677,7 @@ struct Worker {
         }
     }
 
-    // ------------------------------------------------------- registry
-
-    __device__ int scope_best(int e) {
-        int b = 0;
-        if (lane() == 0) b = ld_relaxed(&A.reg[e].best);
-        return uni(b);
-    }
-    __device__ int reg_field(const int* p) {
-        int b = 0;
-        if (lane() == 0) b = ld_relaxed(p);
-        return uni(b);
-    }
+    // ------------------------------------------------------- covers
 
     __device__ void lock(int e) {
         if (lane() == 0) {
@@ -582,61 +688,121 @@ struct Worker {
     }
     __device__ void unlock(int e) {
         wave_sync();
-        if (lane() == 0) st_release(&A.reg[e].lock, 0);
+        if (lane() == 0) {
+            publish_order();
+            st_relaxed(&A.reg[e].lock, 0);
+        }
     }
 
-    __device__ uint32_t* bitmap(int e) { return A.bitmaps + (size_t)e * A.bm_words; }
-
-    // registry entries are only ever accessed with atomics
-    __device__ void init_entry(int e, int best_or_sum, int live, int up, int cover_size,
-                               int nchild, int size) {
-        RegEntry* r = &A.reg[e];
-        st_relaxed(&r->best, best_or_sum);
-        st_relaxed(&r->live, live);
-        st_relaxed(&r->up, up);
-        st_relaxed(&r->lock, 0);
-        st_relaxed(&r->cover_size, cover_size);
-        st_relaxed(&r->nchild, nchild);
-        st_relaxed(&r->size, size);
-        st_relaxed(&r->pad, 0);
-    }
-
-    // write the IN marks of the LDS degree array as bitmap words
+    // the IN marks of the LDS degree array as bitmap words (current view)
     __device__ void write_in_bitmap(uint32_t* bm) {
         const uint32_t l = lane();
-        for (uint32_t wi = l; wi < A.bm_words; wi += 64) {
+        for (uint32_t wi = l; wi < vbw; wi += 64) {
             uint32_t bits = 0;
             const uint32_t v0 = wi * 32u;
             for (uint32_t j = 0; j < 32u; ++j) {
                 uint32_t v = v0 + j;
-                if (v < n && DG::get(deg, v) == DG::IN) bits |= 1u << j;
+                if (v < vn && DG::get(deg, v) == DG::IN) bits |= 1u << j;
             }
             st_coh(&bm[wi], bits);
         }
     }
 
-    // Offer `val` (attained by the cover in LDS, or assembled from the
-    // children of parent entry `from` when from >= 0) as a new Best of scope
-    // entry e.  Returns true if it improved and the cover was written.
+    // Offer `val` as a new Best of scope entry e.  The cover is the LDS
+    // state (from < 0), or is assembled from parent entry `from` and its
+    // children, mapping children with their own view back through their
+    // local-to-parent id maps.  Returns true if the cover was written.
     __device__ bool improve(int e, int val, int from) {
+        int prev_cs = INF;
+        const bool wrote = improve_once(e, val, from, &prev_cs);
+        // PVC (Sec. III-E): a component's better cover travels up the
+        // registry chain at once, so the root learns when it is within k
+        if (wrote && A.pvc && e != 0) propagate_up(e, prev_cs, val);
+        return wrote;
+    }
+
+    // Child entry c's attained cover went from old (INF: none) to val.  Its
+    // parent keeps Sum plus the children's attained covers (att) and the
+    // number of children still without one (unatt); when none is missing,
+    // that total is an attained cover of the parent node and is offered to
+    // the ancestor, and so on up to the root.  Partial totals can only be
+    // too large (every change is a decrease), never too small.
+    __device__ void propagate_up(int c, int old, int val) {
+        for (;;) {
+            const int p = reg_field(&A.reg[c].up);
+            int u = 0;
+            if (lane() == 0) {
+                if (old >= INF) {
+                    add_relaxed(&A.reg[p].att, val);
+                    order_point();
+                    u = add_relaxed(&A.reg[p].unatt, -1) - 1;
+                } else {
+                    add_relaxed(&A.reg[p].att, val - old);
+                    order_point();
+                    u = ld_relaxed(&A.reg[p].unatt);
+                }
+            }
+            u = uni(u);
+            if (u != 0) return;
+            const int total = reg_field(&A.reg[p].att);
+            const int a = reg_field(&A.reg[p].up);
+            int prev = INF;
+            if (!improve_once(a, total, p, &prev)) return;
+            if (a == 0) return;
+            c = a;
+            old = prev;
+            val = total;
+        }
+    }
+
+    __device__ bool improve_once(int e, int val, int from, int* prev_cs) {
         int old = 0;
         if (lane() == 0) old = min_relaxed(&A.reg[e].best, val);
         old = uni(old);
         if (val >= old) return false;
         lock(e);
-        int cs = reg_field(&A.reg[e].cover_size);
+        const int cs = reg_field(&A.reg[e].cover_size);
+        *prev_cs = cs;
         bool wrote = false;
         if (val < cs) {
             uint32_t* dst = bitmap(e);
             if (from < 0) {
                 write_in_bitmap(dst);
             } else {
+                const uint32_t l = lane();
+                const uint32_t ebw = ((uint32_t)reg_field(&A.reg[e].vn) + 31u) / 32u;
                 const int nch = reg_field(&A.reg[from].nchild);
-                for (uint32_t wi = lane(); wi < A.bm_words; wi += 64) {
-                    uint32_t x = ld_coh(&bitmap(from)[wi]);
-                    for (int c = 1; c <= nch; ++c) x |= ld_coh(&bitmap(from + c)[wi]);
-                    st_coh(&dst[wi], x);
+                for (uint32_t wi = l; wi < ebw; wi += 64) VB[wi] = ld_coh(&bitmap(from)[wi]);
+                wave_sync();
+                for (int c = from + 1; c <= from + nch; ++c) {
+                    // in PVC the children may still be improving: read each
+                    // child's cover under its lock (ancestor locks are always
+                    // taken before descendant locks)
+                    if (A.pvc) lock(c);
+                    const int cv = reg_field(&A.reg[c].view);
+                    if (cv == c) {
+                        const uint32_t cn = (uint32_t)reg_field(&A.reg[c].vn);
+                        const uint32_t g_at =
+                            (uint32_t)reg_field(reinterpret_cast<const int*>(&A.reg[c].g_at));
+                        const uint32_t nnz = (uint32_t)reg_field(&A.reg[c].g_nnz);
+                        const uint32_t* l2g = A.arena + g_at + cn + 1u + nnz;
+                        const uint32_t* cb = bitmap(c);
+                        for (uint32_t i = l; i < cn; i += 64) {
+                            if ((ld_coh(&cb[i >> 5]) >> (i & 31u)) & 1u) {
+                                uint32_t w = ld_coh(&l2g[i]);
+                                atomicOr(&VB[w >> 5], 1u << (w & 31u));
+                            }
+                        }
+                    } else {
+                        for (uint32_t wi = l; wi < ebw; wi += 64) {
+                            uint32_t x = ld_coh(&bitmap(c)[wi]);
+                            if (x) atomicOr(&VB[wi], x);
+                        }
+                    }
+                    wave_sync();
+                    if (A.pvc) unlock(c);
                 }
+                for (uint32_t wi = l; wi < ebw; wi += 64) st_coh(&dst[wi], VB[wi]);
             }
             wave_sync();
             if (lane() == 0) st_relaxed(&A.reg[e].cover_size, val);
@@ -653,28 +819,27 @@ struct Worker {
     // descendant of a component adds its Best to the parent's Sum; the last
     // component of a parent offers Sum to the ancestor's Best and finishes
     // the parent node in the ancestor's scope (Sec. III-C).
-    __device__ void complete(int e, bool wrote) {
+    __device__ void complete(int e) {
         while (e != 0) {
             int old = 0;
-            if (lane() == 0) {
-                old = wrote ? add_release(&A.reg[e].live, -1)
-                            : add_relaxed(&A.reg[e].live, -1);
-            }
+            if (lane() == 0) old = add_relaxed(&A.reg[e].live, -1);
             old = uni(old);
             if (old != 1) return;
-            if (lane() == 0) fence_acquire();
+            if (lane() == 0 && A.strong_fences) fence_acquire();
             const int p = reg_field(&A.reg[e].up);
             const int cb = reg_field(&A.reg[e].best);
             if (lane() == 0) {
                 add_relaxed(&A.reg[p].best, cb);
-                old = add_acq_rel(&A.reg[p].live, -1);
+                publish_order();  // the Sum update lands before LiveComps moves
+                old = add_relaxed(&A.reg[p].live, -1);
             }
             old = uni(old);
             if (old != 1) return;
+            if (lane() == 0 && A.strong_fences) fence_acquire();
             wave_sync();
             const int sum = reg_field(&A.reg[p].best);
             const int a = reg_field(&A.reg[p].up);
-            wrote = improve(a, sum, p);
+            improve(a, sum, p);
             e = a;
         }
     }
@@ -692,7 +857,9 @@ struct Worker {
         }
     }
 
-    __device__ bool stop_requested() {
+    __device__ bool stop_requested(bool force) {
+        if (!force && ++since_check < 8) return false;
+        since_check = 0;
         int d = 0;
         if (lane() == 0) d = ld_relaxed(&A.ctl->done);
         return uni(d) != 0;
@@ -704,8 +871,8 @@ struct Worker {
         const uint32_t v = ~(uint32_t)(key & 0xFFFFFFFFull);
         if (scope != 0 && lane() == 0) add_relaxed(&A.reg[scope].live, 1);
         const int ss = s, sc = scope;
-        if (!push_node([&](uint8_t* slot, uint32_t stamp, bool coh) {
-                store_slot(slot, ss, sc, v, stamp, coh);
+        if (!push_node(nl, [&](uint8_t* slot, uint32_t stamp, bool coh) {
+                write_slot(slot, ss, sc, v, nl, stamp, deg, view, vpad, coh);
             }))
             return false;
         if (lane() == 0) R[0] = v;
@@ -761,6 +928,59 @@ struct Worker {
         return nt;
     }
 
+    // Induce component Q[a..b) as a subgraph of its own in the arena:
+    // off[size+1], col[nnz] (local ids = positions in Q), l2g[size] (ids of
+    // the current view).  M is an id map scratch of vn words, CUR one of
+    // size words.  Returns the arena word offset, or NONE if it is full.
+    __device__ uint32_t induce_component(uint32_t a, uint32_t b, uint32_t nnz, uint32_t* M,
+                                         uint32_t* CUR) {
+        const uint32_t l = lane();
+        const uint32_t size = b - a;
+        const uint32_t words = (size + 1u + nnz + size + 31u) & ~31u;  // whole lines
+        uint64_t at = ~0ull;
+        if (l == 0) {
+            uint64_t cur = ld_relaxed(&A.ctl->arena_next);
+            while (cur + words <= A.arena_words) {
+                if (cas_relaxed64(&A.ctl->arena_next, cur, cur + words)) {
+                    at = cur;
+                    break;
+                }
+                cur = ld_relaxed(&A.ctl->arena_next);
+            }
+        }
+        at = uni(at);
+        if (at == ~0ull || at >= 0xFFFFFFFFull) return NONE;
+        uint32_t* g = A.arena + at;
+        for (uint32_t i = a + l; i < b; i += 64) M[Q[i]] = i - a;
+        // offsets: prefix sums of the live degrees, in Q order
+        uint32_t carry = 0;
+        for (uint32_t base = 0; base < size; base += 64) {
+            uint32_t i = base + l;
+            uint32_t d = i < size ? DG::get(deg, Q[a + i]) : 0u;
+            uint32_t incl = wave_incl_scan(d);
+            if (i < size) {
+                CUR[i] = carry + incl - d;
+                st_coh(&g[i], carry + incl - d);
+                st_coh(&g[size + 1u + nnz + i], Q[a + i]);
+            }
+            carry += shfl(incl, 63);
+        }
+        if (l == 0) st_coh(&g[size], carry);
+        wave_sync();
+        // columns: each lane copies the live part of its vertices' rows
+        uint32_t* gc = g + size + 1u;
+        for (uint32_t i = l; i < size; i += 64) {
+            const uint32_t v = Q[a + i];
+            uint32_t pos = CUR[i];
+            for (uint32_t e = voff[v]; e < voff[v + 1]; ++e) {
+                const uint32_t w = vcol[e];
+                if (DG::live(DG::get(deg, w))) st_coh(&gc[pos++], M[w]);
+            }
+        }
+        wave_sync();
+        return (uint32_t)at;
+    }
+
     // Branch on components (Alg. 2): one parent entry plus one child entry
     // per component, best_i = min(best - sum, |V_i| - 1); children other
     // than the first are pushed, the first continues here.  Returns CB_FULL
@@ -770,12 +990,13 @@ struct Worker {
     __device__ int component_branch(uint32_t nc, uint32_t nt) {
         const uint32_t l = lane();
         const uint32_t* NT = R + nc + 1;
+        uint32_t* M = R + A.n_pad + 64u;  // id map scratch (n_pad words)
         // the bound may have improved since the node started: every
         // component needs at least one vertex
         const int bnow = scope_best(scope);
         const int base_sum = s;
         if ((int64_t)base_sum + nt >= (int64_t)bnow) return CB_PRUNED;
-        uint32_t want = (nt + 1u + 3u) & ~3u;  // whole 128-byte lines
+        const uint32_t want = (nt + 1u + 1u) & ~1u;  // whole 128-byte lines
         uint32_t p = NONE;
         if (l == 0) {
             // never bump past the capacity, so a full registry stays full
@@ -791,81 +1012,119 @@ struct Worker {
         }
         p = uni(p);
         if (p == NONE) return CB_FULL;
-        // parent entry: Sum = |S| (with the settled components), LiveComps
-        if (l == 0) init_entry((int)p, base_sum, (int)nt, scope, INF, (int)nt, 0);
+        if (l == 0) init_entry((int)p, base_sum, (int)nt, scope, INF, (int)nt, 0, view, (int)vn, 0u, 0);
         write_in_bitmap(bitmap((int)p));
-        // child entries and their initial covers (V_i minus one vertex)
+        // child entries, their graph views and their initial covers (the
+        // component minus one vertex: |V_i| - 1 is always attained)
         for (uint32_t j = 0; j < nt; ++j) {
             const uint32_t c = NT[j];
             const uint32_t a = R[c], b = R[c + 1], size = b - a;
             int bi = bnow - base_sum;
             const bool attained = (int)size - 1 <= bi;
             if (attained) bi = (int)size - 1;
-            uint32_t mx = 0;
-            for (uint32_t i = a + l; i < b; i += 64) mx = Q[i] > mx ? Q[i] : mx;
-            mx = wave_max(mx);
+            uint32_t dsum = 0;
+            for (uint32_t i = a + l; i < b; i += 64) dsum += DG::get(deg, Q[i]);
+            const uint32_t nnz = wave_sum(dsum);
+            const int e = (int)(p + 1u + j);
+            uint32_t g_at = NONE;
+            if (size + 1u + nnz <= A.gcache_words && size < vn) g_at = induce_component(a, b, nnz, M, L);
+            const bool own = g_at != NONE;
             if (l == 0)
-                init_entry((int)(p + 1 + j), bi, 1, (int)p, attained ? (int)size - 1 : INF, 0,
-                           (int)size);
+                init_entry(e, bi, 1, (int)p, attained ? (int)size - 1 : INF, 0, (int)size,
+                           own ? e : view, own ? (int)size : (int)vn, own ? g_at : 0u,
+                           own ? (int)nnz : 0);
             if (attained) {
-                for (uint32_t i = l; i < bw; i += 64) VB[i] = 0u;
-                wave_sync();
-                for (uint32_t i = a + l; i < b; i += 64) {
-                    uint32_t v = Q[i];
-                    if (v != mx) atomicOr(&VB[v >> 5], 1u << (v & 31u));
+                uint32_t* bm = bitmap(e);
+                if (own) {
+                    const uint32_t w = (size + 31u) / 32u;
+                    for (uint32_t i = l; i < w; i += 64) {
+                        uint32_t bits = ~0u;
+                        if (i == w - 1u && (size & 31u)) bits = (1u << (size & 31u)) - 1u;
+                        if (i == 0) bits &= ~1u;  // all but local vertex 0
+                        st_coh(&bm[i], bits);
+                    }
+                } else {
+                    for (uint32_t i = l; i < vbw; i += 64) VB[i] = 0u;
+                    wave_sync();
+                    for (uint32_t i = a + 1u + l; i < b; i += 64) {
+                        uint32_t v = Q[i];
+                        atomicOr(&VB[v >> 5], 1u << (v & 31u));
+                    }
+                    wave_sync();
+                    for (uint32_t i = l; i < vbw; i += 64) st_coh(&bm[i], VB[i]);
                 }
-                wave_sync();
-                uint32_t* bm = bitmap((int)(p + 1 + j));
-                for (uint32_t i = l; i < A.bm_words; i += 64) st_coh(&bm[i], VB[i]);
+            }
+            if (own) ++lviews;
+            if (l == 0) {
+                if (attained) add_relaxed(&A.reg[p].att, (int)size - 1);
+                else add_relaxed(&A.reg[p].unatt, 1);
             }
             wave_sync();
         }
-        // entries and initial covers must be visible to whichever worker
-        // finishes the last component
-        wave_sync();
-        if (l == 0) fence_release();
+        if (l == 0) add_relaxed(&A.reg[p].att, base_sum);
+        // entries, covers and graphs are complete before any child can run
+        if (l == 0) publish_order();
         cbr += 1;
         comps += nt;
-        // children 1..nt-1 go out as nodes holding only their component
+        // children 1..nt-1 go out as nodes holding only their component,
+        // built in L (free until child 0 rebuilds it)
+        D* cd = reinterpret_cast<D*>(L);
         for (uint32_t j = nt - 1; j >= 1; --j) {
             const uint32_t c = NT[j];
-            const uint32_t a = R[c], b = R[c + 1];
-            const int sc = (int)(p + 1 + j);
-            // the child's degree array: this component only, built in L
-            // (free until child 0 rebuilds it)
-            D* cd = reinterpret_cast<D*>(L);
+            const uint32_t a = R[c], b = R[c + 1], size = b - a;
+            const int e = (int)(p + 1u + j);
+            const bool own = reg_field(&A.reg[e].view) == e;
+            const uint32_t cpad = own ? ((size + 63u) & ~63u) : vpad;
             {
                 uint4* z = reinterpret_cast<uint4*>(cd);
-                const uint32_t nv = (n_pad * (uint32_t)sizeof(D)) / 16u;
+                const uint32_t nv = (cpad * (uint32_t)sizeof(D)) / 16u;
                 for (uint32_t i = l; i < nv; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
                 wave_sync();
                 for (uint32_t i = a + l; i < b; i += 64) {
                     uint32_t v = Q[i];
-                    cd[v] = (D)DG::get(deg, v);
+                    cd[own ? i - a : v] = (D)DG::get(deg, v);
                 }
                 wave_sync();
             }
-            bool ok = push_node([&](uint8_t* slot, uint32_t stamp, bool coh) {
-                write_slot(slot, 0, sc, NONE, b - a, stamp, cd, coh);
+            const int vw = own ? e : view;
+            bool ok = push_node(size, [&](uint8_t* slot, uint32_t stamp, bool coh) {
+                write_slot(slot, 0, e, NONE, size, stamp, cd, vw, cpad, coh);
             });
             if (!ok) return CB_OK;  // error flagged; the next node stops
         }
-        // child 0 continues in LDS: keep only its component, S restarts
+        // child 0 continues in LDS: only its component, S restarts
         {
             const uint32_t c = NT[0];
-            const uint32_t a = R[c], b = R[c + 1];
-            for (uint32_t i = l; i < bw; i += 64) VB[i] = 0u;
-            wave_sync();
-            for (uint32_t i = a + l; i < b; i += 64) {
-                uint32_t v = Q[i];
-                atomicOr(&VB[v >> 5], 1u << (v & 31u));
+            const uint32_t a = R[c], b = R[c + 1], size = b - a;
+            const int e = (int)(p + 1u);
+            const bool own = reg_field(&A.reg[e].view) == e;
+            if (own) {
+                const uint32_t cpad = (size + 63u) & ~63u;
+                uint4* z = reinterpret_cast<uint4*>(cd);
+                const uint32_t nv = (cpad * (uint32_t)sizeof(D)) / 16u;
+                for (uint32_t i = l; i < nv; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+                wave_sync();
+                for (uint32_t i = a + l; i < b; i += 64) cd[i - a] = (D)DG::get(deg, Q[i]);
+                wave_sync();
+                const uint64_t* s8 = reinterpret_cast<const uint64_t*>(cd);
+                uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
+                for (uint32_t i = l; i < (cpad * (uint32_t)sizeof(D)) / 8u; i += 64) d8[i] = s8[i];
+                wave_sync();
+                load_view(e);
+            } else {
+                for (uint32_t i = l; i < vbw; i += 64) VB[i] = 0u;
+                wave_sync();
+                for (uint32_t i = a + l; i < b; i += 64) {
+                    uint32_t v = Q[i];
+                    atomicOr(&VB[v >> 5], 1u << (v & 31u));
+                }
+                wave_sync();
+                for (uint32_t v = l; v < vn; v += 64)
+                    if (!((VB[v >> 5] >> (v & 31u)) & 1u)) DG::set(deg, v, 0u);
+                wave_sync();
             }
-            wave_sync();
-            for (uint32_t v = l; v < n; v += 64)
-                if (!((VB[v >> 5] >> (v & 31u)) & 1u)) DG::set(deg, v, 0u);
-            wave_sync();
             s = 0;
-            scope = (int)(p + 1);
+            scope = e;
             build_live();
             known_connected = true;
         }
@@ -874,55 +1133,68 @@ struct Worker {
 
     // Process one node and, depth-first, its first children in place.
     __device__ void process() {
+        bool recount = true;
         for (;;) {
-            count_node();
-            if (stop_requested()) return;
+            if (recount) count_node();
+            recount = true;
+            if (stop_requested(false)) return;
             best = scope_best(scope);
-            if (!reduce()) {
-                complete(scope, false);
+            const bool alive = reduce();
+            charge(CYC_REDUCE);
+            if (!alive) {
+                complete(scope);
+                charge(CYC_COMPLETE);
                 return;
             }
             const int64_t b = (int64_t)best - s - 1;
             const uint64_t E = e2 / 2u;
             if (b < 0 || (int64_t)E > b * b) {
-                complete(scope, false);
+                complete(scope);
+                charge(CYC_COMPLETE);
                 return;
             }
             if (E == 0) {
-                bool w = improve(scope, s, -1);
-                complete(scope, w);
+                improve(scope, s, -1);
+                complete(scope);
+                charge(CYC_COMPLETE);
                 return;
             }
             if (!(A.flags & VC_OPT_NO_COMPONENTS) && !known_connected) {
                 const uint32_t nc = find_components();
                 const uint32_t nt = settle_simple_components(nc);
                 if (nt != nc) recompact();
+                charge(CYC_COMPONENTS);
                 if (s >= best) {
-                    complete(scope, false);
+                    complete(scope);
+                    charge(CYC_COMPLETE);
                     return;
                 }
                 if (nt == 0) {
-                    if (s < best) {
-                        bool w = improve(scope, s, -1);
-                        complete(scope, w);
-                    } else {
-                        complete(scope, false);
-                    }
+                    improve(scope, s, -1);
+                    complete(scope);
+                    charge(CYC_COMPLETE);
                     return;
                 }
                 if (nt == 1) {
                     known_connected = true;
-                    if (nt != nc) continue;  // re-run the rules on what is left
+                    if (nt != nc) {
+                        recount = false;  // same node, rules again with the new bound
+                        continue;
+                    }
                 } else {
                     const int cb = component_branch(nc, nt);
+                    charge(CYC_COMPONENTS);
                     if (cb == CB_OK) continue;
                     if (cb == CB_PRUNED) {
-                        complete(scope, false);
+                        complete(scope);
+                        charge(CYC_COMPLETE);
                         return;
                     }
                 }
             }
-            if (!vertex_branch()) return;
+            const bool ok = vertex_branch();
+            charge(CYC_BRANCH);
+            if (!ok) return;
         }
     }
 
@@ -933,42 +1205,61 @@ struct Worker {
             add_relaxed(&A.ctl->components, comps);
             add_relaxed(&A.ctl->donations, dons);
             add_relaxed(&A.ctl->pushes, pushes);
+            add_relaxed(&A.ctl->local_views, lviews);
+            for (int i = 0; i < 6; ++i) add_relaxed(&A.ctl->cyc[i], cyc[i]);
         }
     }
 
     __device__ void run() {
         bool busy = false;
         for (;;) {
-            if (top > 0) {
-                if (stop_requested()) break;
+            if (top > bot) {
+                if (stop_requested(true)) break;
                 --top;
                 begin_node(copy_slot(stack + (size_t)top * A.slot_bytes));
+                if (top == bot) bot = top = 0;
+                charge(CYC_FETCH);
             } else {
+                bot = top = 0;
                 if (busy && lane() == 0) add_relaxed(&A.ctl->outstanding, -1);
                 busy = false;
                 if (lane() == 0) add_relaxed(&A.ctl->idle, 1);
                 uint32_t spins = 0;
                 bool got = false, quit = false;
                 const uint64_t t_idle = wall_clock64();
-                for (;;) {
-                    int d = 0, outst = 0;
-                    uint64_t h = 0, t = 0;
-                    if (lane() == 0) {
-                        d = ld_relaxed(&A.ctl->done);
-                        outst = ld_relaxed(&A.ctl->outstanding);
-                        h = ld_relaxed(&A.ctl->wl_head);
-                        t = ld_relaxed(&A.ctl->wl_tail);
-                    }
-                    d = uni(d);
-                    outst = uni(outst);
-                    h = uni(h);
+                // poll the queue tail only; head, the outstanding count and
+                // the stop flag are read when it moved or every 16th round
+                uint64_t seen_tail = ~0ull;
+                for (uint32_t round = 0;; ++round) {
+                    uint64_t t = 0;
+                    if (lane() == 0) t = ld_relaxed(&A.ctl->wl_tail);
                     t = uni(t);
-                    if (d) { quit = true; break; }
-                    if (t > h) {
-                        if (wl_take()) { got = true; break; }
-                    } else if (outst == 0) {
-                        quit = true;
-                        break;
+                    if (t != seen_tail || (round & 15u) == 0) {
+                        seen_tail = t;
+                        int d = 0, outst = 0;
+                        uint64_t h = 0;
+                        if (lane() == 0) {
+                            d = ld_relaxed(&A.ctl->done);
+                            h = ld_relaxed(&A.ctl->wl_head);
+                            outst = ld_relaxed(&A.ctl->outstanding);
+                        }
+                        d = uni(d);
+                        outst = uni(outst);
+                        h = uni(h);
+                        if (d) {
+                            quit = true;
+                            break;
+                        }
+                        if (t > h) {
+                            if (wl_take()) {
+                                got = true;
+                                break;
+                            }
+                            spins = 0;
+                        } else if (outst == 0) {
+                            quit = true;
+                            break;
+                        }
                     }
                     if (wall_clock64() - t_idle > A.watchdog_ticks) {
                         // waited far longer than any node takes: give up
@@ -979,6 +1270,7 @@ struct Worker {
                     if (lane() == 0) backoff(spins);
                 }
                 if (lane() == 0) add_relaxed(&A.ctl->idle, -1);
+                charge(CYC_IDLE);
                 if (quit) break;
                 busy = got;
             }
@@ -988,10 +1280,10 @@ struct Worker {
     }
 };
 
-template <typename D, typename C>
+template <typename D>
 __global__ void __launch_bounds__(64) search_kernel(SearchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    Worker<D, C> w(a, lds);
+    Worker<D> w(a, lds);
     w.run();
 }
 
@@ -1011,6 +1303,7 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         h->branch_v = NONE;
         h->nlive = a.n;
         h->stamp = 0;
+        h->view = 0;
         *reinterpret_cast<uint32_t*>(a.wl_slots + a.slot_bytes - 16u) = 0u;
         Ctl* c = a.ctl;
         c->wl_head = 0;
@@ -1019,10 +1312,12 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         c->idle = 0;
         c->done = 0;
         c->err = 0;
-        c->reg_next = 4;  // entry 0 is the root scope; allocations are 4-aligned
+        c->reg_next = 2;  // entry 0 is the root scope; allocations are 2-aligned
+        c->arena_next = 0;
         c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
-        c->stale = 0;
-        RegEntry r;
+        c->stale = c->local_views = 0;
+        for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
+        RegEntry r = {};
         r.best = best0;
         r.live = 1;
         r.up = -1;
@@ -1030,44 +1325,34 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         r.cover_size = INF;
         r.nchild = 0;
         r.size = (int)a.n;
-        r.pad = 0;
+        r.view = 0;
+        r.vn = (int)a.n;
         a.reg[0] = r;
     }
 }
 
-template <typename D, typename C>
+template <typename D>
 static hipError_t launch_t(const SearchArgs& a, uint32_t workers, hipStream_t st) {
-    hipLaunchKernelGGL((search_kernel<D, C>), dim3(workers), dim3(64), a.lds_bytes, st, a);
+    hipLaunchKernelGGL(search_kernel<D>, dim3(workers), dim3(64), a.lds_bytes, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_search(const SearchArgs& a, uint32_t deg_bytes, uint32_t col_bytes,
-                         uint32_t workers, hipStream_t st) {
-    if (col_bytes == 2) {
-        if (deg_bytes == 1) return launch_t<uint8_t, uint16_t>(a, workers, st);
-        if (deg_bytes == 2) return launch_t<uint16_t, uint16_t>(a, workers, st);
-        return launch_t<uint32_t, uint16_t>(a, workers, st);
-    }
-    if (deg_bytes == 1) return launch_t<uint8_t, uint32_t>(a, workers, st);
-    if (deg_bytes == 2) return launch_t<uint16_t, uint32_t>(a, workers, st);
-    return launch_t<uint32_t, uint32_t>(a, workers, st);
+hipError_t launch_search(const SearchArgs& a, uint32_t deg_bytes, uint32_t workers,
+                         hipStream_t st) {
+    if (deg_bytes == 1) return launch_t<uint8_t>(a, workers, st);
+    if (deg_bytes == 2) return launch_t<uint16_t>(a, workers, st);
+    return launch_t<uint32_t>(a, workers, st);
 }
 
-template <typename D, typename C>
+template <typename D>
 static hipError_t occ_t(uint32_t lds_bytes, int* bpc) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, search_kernel<D, C>, 64, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, search_kernel<D>, 64, lds_bytes);
 }
 
-hipError_t search_occupancy(uint32_t deg_bytes, uint32_t col_bytes, uint32_t lds_bytes,
-                            int* bpc) {
-    if (col_bytes == 2) {
-        if (deg_bytes == 1) return occ_t<uint8_t, uint16_t>(lds_bytes, bpc);
-        if (deg_bytes == 2) return occ_t<uint16_t, uint16_t>(lds_bytes, bpc);
-        return occ_t<uint32_t, uint16_t>(lds_bytes, bpc);
-    }
-    if (deg_bytes == 1) return occ_t<uint8_t, uint32_t>(lds_bytes, bpc);
-    if (deg_bytes == 2) return occ_t<uint16_t, uint32_t>(lds_bytes, bpc);
-    return occ_t<uint32_t, uint32_t>(lds_bytes, bpc);
+hipError_t search_occupancy(uint32_t deg_bytes, uint32_t lds_bytes, int* bpc) {
+    if (deg_bytes == 1) return occ_t<uint8_t>(lds_bytes, bpc);
+    if (deg_bytes == 2) return occ_t<uint16_t>(lds_bytes, bpc);
+    return occ_t<uint32_t>(lds_bytes, bpc);
 }
 
 hipError_t launch_search_init(const SearchArgs& a, int best0, uint32_t deg_bytes,

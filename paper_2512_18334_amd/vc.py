@@ -24,6 +24,8 @@ VC_OPT_NO_COMPONENTS = 1
 VC_OPT_NO_LOAD_BALANCE = 2
 VC_OPT_VALIDATE_SKIP = 4
 
+CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]
+
 EXPORTS = ["vc_ctx_create", "vc_ctx_destroy", "vc_validate", "vc_min",
            "vc_param", "vc_last_stats", "vc_status_str"]
 
@@ -38,14 +40,16 @@ class vc_opts(ctypes.Structure):
     _fields_ = [("workers", ctypes.c_uint32), ("donate_slack", ctypes.c_uint32),
                 ("worklist_cap", ctypes.c_uint32), ("registry_cap", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("node_limit", ctypes.c_uint64),
-                ("flags", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
+                ("donate_min", ctypes.c_uint32), ("gcache_words", ctypes.c_uint32)]
 
 
 class vc_stats(ctypes.Structure):
     _fields_ = [("tree_nodes", ctypes.c_uint64),
                 ("component_branches", ctypes.c_uint64),
                 ("components", ctypes.c_uint64), ("donations", ctypes.c_uint64),
-                ("pushes", ctypes.c_uint64),
+                ("pushes", ctypes.c_uint64), ("local_views", ctypes.c_uint64),
+                ("cycles", ctypes.c_uint64 * 6),
                 ("n_input", ctypes.c_uint32), ("n_kernel", ctypes.c_uint32),
                 ("nnz_kernel", ctypes.c_uint64), ("forced_root", ctypes.c_uint32),
                 ("greedy_size", ctypes.c_uint32),
@@ -161,10 +165,12 @@ class Solver:
     def __init__(self, device: int = 0, stream=None, workers: int = 0,
                  donate_slack: int = 0, worklist_cap: int = 0,
                  registry_cap: int = 0, hbm_budget: int = 0,
-                 node_limit: int = 0, flags: int = 0, watchdog_ms: int = 0):
+                 node_limit: int = 0, flags: int = 0, watchdog_ms: int = 0,
+                 donate_min: int = 0, gcache_words: int = 0):
         lib = load()
         self._opts = vc_opts(workers, donate_slack, worklist_cap, registry_cap,
-                             hbm_budget, node_limit, flags, watchdog_ms)
+                             hbm_budget, node_limit, flags, watchdog_ms,
+                             donate_min, gcache_words)
         h = ctypes.c_void_p()
         st = lib.vc_ctx_create(int(device), stream, ctypes.byref(self._opts),
                                ctypes.byref(h))
@@ -202,7 +208,9 @@ class Solver:
     def stats(self) -> dict:
         s = vc_stats()
         _check(load().vc_last_stats(self._h, ctypes.byref(s)), "vc_last_stats")
-        return {f: getattr(s, f) for f, _ in vc_stats._fields_}
+        out = {f: getattr(s, f) for f, _ in vc_stats._fields_}
+        out["cycles"] = dict(zip(CYCLE_NAMES, list(s.cycles)))
+        return out
 
     def mvc(self, g, want_cover: bool = True) -> Result:
         c, keep = self._csr(g)
