@@ -74,6 +74,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB device to "
+                         "device once: a kernel of known traffic that scales "
+                         "the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -110,13 +114,13 @@ def main():
     nodes = sum(s["tree_nodes"] for s in stats)
     ms_step = el * 1e3 / args.steps
     search_ms = sum(s["ms_search"] for s in stats) / len(stats)
-    # algorithmic HBM bytes of one search launch: every pushed node slot is
-    # written once and read once, the root slot is read once, and each
-    # registered component writes one registry entry and one cover bitmap
+    # algorithmic HBM bytes of one search launch: every node written to a
+    # slot (header, the degree array of its graph view, trailer) is read back
+    # once, the root node is read once, and the registry entries, cover
+    # bitmaps and per-component graphs are written (device counters)
     s0 = stats[-1]
-    alg_bytes = sum((2 * s["pushes"] + 1) * s["slot_bytes"]
-                    + (s["components"] + s["component_branches"])
-                    * (32 + s["bitmap_bytes"]) for s in stats) / len(stats)
+    alg_bytes = sum(2 * s["bytes_nodes"] + s["slot_bytes"] + s["bytes_registry"]
+                    for s in stats) / len(stats)
     achieved = alg_bytes / (search_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -142,6 +146,13 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(alg_bytes)},
     }
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["config"]["calibration_copy_mib"] = args.copy_mib
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
     solver.close()

@@ -85,8 +85,10 @@ typedef struct {
  *   watchdog_ms   a worker that has waited this long for work while work
  *                 is still outstanding stops the search with VC_EDEVICE
  *                 (default 120000).
- *   donate_min    nodes with fewer live vertices are never donated (their
- *                 subtrees are too small to pay for the move; default 64).
+ *   donate_min    a node with fewer live vertices is never donated (its
+ *                 subtree is too small to pay for the move).  A donating
+ *                 worker gives away its oldest pending node, so the test
+ *                 applies to that node (default 24).
  *   gcache_words  LDS graph cache per worker, in 32-bit words: components
  *                 whose induced subgraph fits are re-induced with local ids
  *                 (default: the most that still fits three workers per CU).
@@ -113,6 +115,9 @@ typedef struct {
     uint64_t pushes;             /* node slots written to HBM (stacks and
                                     worklist); each is read back once       */
     uint64_t local_views;        /* components re-induced with local ids   */
+    uint64_t bytes_nodes;        /* bytes written into node slots in HBM   */
+    uint64_t bytes_registry;     /* bytes of registry entries, cover bitmaps
+                                    and per-component graphs written        */
     uint64_t cycles[6];          /* shader cycles summed over workers:
                                     fetch, rules, components, vertex branch,
                                     registry completion, idle (Sec. V-D)    */

@@ -401,7 +401,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         a.gcache_words = gwords;
         a.arena = (uint32_t*)c->arena.p;
         a.arena_words = arena_words;
-        a.donate_min = c->opts.donate_min ? c->opts.donate_min : 64u;
+        a.donate_min = c->opts.donate_min ? c->opts.donate_min : 24u;
         a.strong_fences = getenv("VC_STRONG_FENCES") ? 1u : 0u;
         a.pvc = pvc;
         a.k = pvc ? (int)k - (int)sroot : 0;
@@ -426,6 +426,8 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         stv.pushes = ctl.pushes;
         stv.local_views = ctl.local_views;
         for (int i = 0; i < 6; ++i) stv.cycles[i] = ctl.cyc[i];
+        stv.bytes_nodes = ctl.bytes_nodes;
+        stv.bytes_registry = ctl.bytes_registry;
         stv.slot_bytes = slot_bytes;
         stv.bitmap_bytes = 4u * bm_words;
         float ms = 0;

@@ -27,54 +27,60 @@ __device__ __forceinline__ uint32_t shfl(uint32_t x, uint32_t src) {
     return (uint32_t)__shfl((int)x, (int)src, 64);
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
-    return x;
-}
+// Cross-lane scans with DPP: row_shr by 1, 2, 4, 8 inside each 16-lane row,
+// then row_bcast 15 and 31 carry rows 0 -> 1, 2 -> 3 and rows 0-1 -> 2-3.
+// Lanes without a source read `id` (0 for sums, 0 / ~0 for max / min).
+#define VC_DPP_SCAN(x, op, id)                                                     \
+    do {                                                                           \
+        uint32_t _t;                                                               \
+        _t = __builtin_amdgcn_update_dpp(id, x, 0x111, 0xf, 0xf, false); x = op(x, _t); \
+        _t = __builtin_amdgcn_update_dpp(id, x, 0x112, 0xf, 0xf, false); x = op(x, _t); \
+        _t = __builtin_amdgcn_update_dpp(id, x, 0x114, 0xf, 0xf, false); x = op(x, _t); \
+        _t = __builtin_amdgcn_update_dpp(id, x, 0x118, 0xf, 0xf, false); x = op(x, _t); \
+        _t = __builtin_amdgcn_update_dpp(id, x, 0x142, 0xa, 0xf, false); x = op(x, _t); \
+        _t = __builtin_amdgcn_update_dpp(id, x, 0x143, 0xc, 0xf, false); x = op(x, _t); \
+    } while (0)
 
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-__device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint64_t y = __shfl_xor(x, o, 64);
-        x = y > x ? y : x;
-    }
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t y = (uint32_t)__shfl_xor((int)x, o, 64);
-        x = y < x ? y : x;
-    }
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t y = (uint32_t)__shfl_xor((int)x, o, 64);
-        x = y > x ? y : x;
-    }
-    return x;
-}
+__device__ __forceinline__ uint32_t op_add(uint32_t a, uint32_t b) { return a + b; }
+__device__ __forceinline__ uint32_t op_max(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint32_t op_min(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
 // inclusive prefix sum across the 64 lanes
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-    const uint32_t l = lane();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
-        if (l >= (uint32_t)o) x += y;
-    }
+    VC_DPP_SCAN(x, op_add, 0u);
     return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+    VC_DPP_SCAN(x, op_add, 0u);
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+    VC_DPP_SCAN(x, op_max, 0u);
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+    VC_DPP_SCAN(x, op_min, 0xFFFFFFFFu);
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+    // exact modulo 2^64: the two low 16-bit fields cannot carry out of 32
+    // bits over 64 lanes, the high word wraps exactly as the full sum does
+    const uint64_t a = wave_sum((uint32_t)(x & 0xFFFFu));
+    const uint64_t b = wave_sum((uint32_t)((x >> 16) & 0xFFFFu));
+    const uint64_t c = wave_sum((uint32_t)(x >> 32));
+    return a + (b << 16) + (c << 32);
+}
+
+// max of a 64-bit key: the largest high word, then the largest low word
+// among the lanes that hold it
+__device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
+    const uint32_t hi = wave_max((uint32_t)(x >> 32));
+    const uint32_t lo = wave_max((uint32_t)(x >> 32) == hi ? (uint32_t)x : 0u);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // all lanes agree (wave is the whole workgroup: a barrier is one wave sync)

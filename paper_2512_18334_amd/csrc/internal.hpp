@@ -85,7 +85,9 @@ struct Ctl {
     // of Sec. V-D): fetching nodes, rules, component search and
     // registration, vertex branching, registry completion, waiting for work
     uint64_t cyc[6];
-    uint64_t _p7[10];
+    uint64_t bytes_nodes;     // bytes written into node slots (each is read back once)
+    uint64_t bytes_registry;  // bytes of registry entries, cover bitmaps and arena graphs written
+    uint64_t _p7[8];
 };
 enum { CYC_FETCH = 0, CYC_REDUCE, CYC_COMPONENTS, CYC_BRANCH, CYC_COMPLETE, CYC_IDLE };
 

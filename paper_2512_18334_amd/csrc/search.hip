@@ -101,6 +101,7 @@ struct Worker {
     uint64_t nodes, cbr, comps, dons, pushes, lviews, nodes_flushed;
     uint64_t cyc[6];
     uint64_t t_mark;
+    uint64_t b_nodes, b_reg;  // algorithmic bytes written (node slots; registry)
 
     __device__ Worker(const SearchArgs& a, uint8_t* lds) : A(a) {
         deg = reinterpret_cast<D*>(lds);
@@ -112,6 +113,7 @@ struct Worker {
         G = reinterpret_cast<uint32_t*>(lds + a.lds_G);
         stack = a.stacks + (size_t)blockIdx.x * a.stack_depth * a.slot_bytes;
         bot = top = 0;
+        b_nodes = b_reg = 0;
         for (int i = 0; i < 6; ++i) cyc[i] = 0;
         t_mark = clock64();
         since_check = 0;
@@ -429,6 +431,7 @@ struct Worker {
         const uint32_t nw = (npad * (uint32_t)sizeof(D)) / 8u;
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(src);
         uint64_t* d8 = reinterpret_cast<uint64_t*>(slot + sizeof(SlotHdr));
+        b_nodes += 8ull * nw + sizeof(SlotHdr) + 16u;
         if (coh) {
             if (l < 8) st_coh(&h[l], hw);
             if (l < 4) st_coh(&tr[l], l == 0 ? stamp : 0u);
@@ -616,7 +619,15 @@ struct Worker {
     template <typename Fill>
     __device__ bool push_node(uint32_t live, Fill&& fill) {
         ++pushes;
-        if (hungry(live)) {
+        // the threshold applies to what would be donated: the oldest
+        // pending node when there is one, else this one
+        uint32_t cand = live;
+        if (top > bot) {
+            uint32_t nlv = 0;
+            if (lane() == 0) nlv = reinterpret_cast<const SlotHdr*>(stack + (size_t)bot * A.slot_bytes)->nlive;
+            cand = uni(nlv);
+        }
+        if (hungry(cand)) {
             // give away the oldest pending node (it roots the largest subtree)
             // when there is one, else this one
             uint64_t pos = wl_reserve();
@@ -666,6 +677,7 @@ struct Worker {
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(src + sizeof(SlotHdr));
         uint64_t* d8 = reinterpret_cast<uint64_t*>(dst + sizeof(SlotHdr));
         for (uint32_t i = l; i < nw; i += 64) st_coh64(&d8[i], s8[i]);
+        b_nodes += 8ull * nw + sizeof(SlotHdr) + 16u;
         ++bot;
         if (bot == top) bot = top = 0;
     }
@@ -806,6 +818,7 @@ struct Worker {
             }
             wave_sync();
             if (lane() == 0) st_relaxed(&A.reg[e].cover_size, val);
+            b_reg += 4ull * vbw;
             wrote = true;
         }
         unlock(e);
@@ -951,6 +964,7 @@ struct Worker {
         at = uni(at);
         if (at == ~0ull || at >= 0xFFFFFFFFull) return NONE;
         uint32_t* g = A.arena + at;
+        b_reg += 4ull * (size + 1u + nnz + size);
         for (uint32_t i = a + l; i < b; i += 64) M[Q[i]] = i - a;
         // offsets: prefix sums of the live degrees, in Q order
         uint32_t carry = 0;
@@ -1014,6 +1028,7 @@ struct Worker {
         if (p == NONE) return CB_FULL;
         if (l == 0) init_entry((int)p, base_sum, (int)nt, scope, INF, (int)nt, 0, view, (int)vn, 0u, 0);
         write_in_bitmap(bitmap((int)p));
+        b_reg += (uint64_t)(nt + 1u) * sizeof(RegEntry) + 4ull * vbw * (nt + 1u);
         // child entries, their graph views and their initial covers (the
         // component minus one vertex: |V_i| - 1 is always attained)
         for (uint32_t j = 0; j < nt; ++j) {
@@ -1207,6 +1222,8 @@ struct Worker {
             add_relaxed(&A.ctl->pushes, pushes);
             add_relaxed(&A.ctl->local_views, lviews);
             for (int i = 0; i < 6; ++i) add_relaxed(&A.ctl->cyc[i], cyc[i]);
+            add_relaxed(&A.ctl->bytes_nodes, b_nodes);
+            add_relaxed(&A.ctl->bytes_registry, b_reg);
         }
     }
 
@@ -1317,6 +1334,7 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
         c->stale = c->local_views = 0;
         for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
+        c->bytes_nodes = c->bytes_registry = 0;
         RegEntry r = {};
         r.best = best0;
         r.live = 1;

@@ -49,6 +49,7 @@ class vc_stats(ctypes.Structure):
                 ("component_branches", ctypes.c_uint64),
                 ("components", ctypes.c_uint64), ("donations", ctypes.c_uint64),
                 ("pushes", ctypes.c_uint64), ("local_views", ctypes.c_uint64),
+                ("bytes_nodes", ctypes.c_uint64), ("bytes_registry", ctypes.c_uint64),
                 ("cycles", ctypes.c_uint64 * 6),
                 ("n_input", ctypes.c_uint32), ("n_kernel", ctypes.c_uint32),
                 ("nnz_kernel", ctypes.c_uint64), ("forced_root", ctypes.c_uint32),
