@@ -73,7 +73,7 @@ typedef struct {
 /*
  * Tuning knobs.  Zero in any field selects the library default.
  *   workers       persistent search workers (one 64-lane wave each); the
- *                 default fills every compute unit within the LDS and HBM
+ *                 default is one per compute unit, within the LDS and HBM
  *                 budgets.
  *   donate_slack  a worker donates a child to the shared worklist while
  *                 idle workers outnumber queued nodes by more than this.
@@ -88,7 +88,7 @@ typedef struct {
  *   donate_min    a node with fewer live vertices is never donated (its
  *                 subtree is too small to pay for the move).  A donating
  *                 worker gives away its oldest pending node, so the test
- *                 applies to that node (default 24).
+ *                 applies to that node (default 48).
  *   gcache_words  LDS graph cache per worker, in 32-bit words: components
  *                 whose induced subgraph fits are re-induced with local ids
  *                 (default: the most that still fits three workers per CU).

@@ -347,7 +347,11 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         int bpc = 0;
         HIPCHK(search_occupancy(deg_bytes, lp.bytes, &bpc));
         if (bpc < 1) return VC_ERANGE;
-        uint32_t workers = c->opts.workers ? c->opts.workers : (uint32_t)(bpc * c->cus);
+        // one worker per CU by default: the waves of a CU share its LDS and
+        // issue slots, and more workers than the tree keeps busy only add
+        // donation and polling traffic
+        uint32_t workers = c->opts.workers ? c->opts.workers : (uint32_t)c->cus;
+        if (workers > (uint32_t)(bpc * c->cus)) workers = (uint32_t)(bpc * c->cus);
         const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes + 16u;
         uint32_t depth = std::min<uint32_t>(np, (uint32_t)kbest0) + np / 4u + 16u;
         const uint64_t budget = c->opts.hbm_budget ? c->opts.hbm_budget : (48ull << 30);
@@ -401,7 +405,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         a.gcache_words = gwords;
         a.arena = (uint32_t*)c->arena.p;
         a.arena_words = arena_words;
-        a.donate_min = c->opts.donate_min ? c->opts.donate_min : 24u;
+        a.donate_min = c->opts.donate_min ? c->opts.donate_min : 48u;
         a.strong_fences = getenv("VC_STRONG_FENCES") ? 1u : 0u;
         a.pvc = pvc;
         a.k = pvc ? (int)k - (int)sroot : 0;
