@@ -69,6 +69,8 @@ typedef struct {
 #define VC_OPT_NO_LOAD_BALANCE 2u /* no worklist donation: every child stays
                                      on its worker's own stack              */
 #define VC_OPT_VALIDATE_SKIP 4u /* trust the caller: skip the CSR checks     */
+#define VC_OPT_NO_GRAPH 8u      /* batches: launch the kernels one by one
+                                   instead of replaying a captured hipGraph */
 
 /*
  * Tuning knobs.  Zero in any field selects the library default.
@@ -81,7 +83,8 @@ typedef struct {
  *   registry_cap  component branch registry capacity in entries; when full,
  *                 the search branches on a vertex instead (still exact).
  *   hbm_budget    bytes of device memory the search may use.
- *   node_limit    stop with VC_ETIMEDOUT after this many tree nodes.
+ *   node_limit    stop with VC_ETIMEDOUT after this many tree nodes (in a
+ *                 batch: per instance, and only that instance stops).
  *   watchdog_ms   a worker that has waited this long for work while work
  *                 is still outstanding stops the search with VC_EDEVICE
  *                 (default 120000).
@@ -177,6 +180,60 @@ vc_status vc_min(vc_ctx *ctx, const vc_csr *g, uint32_t *size,
  */
 vc_status vc_param(vc_ctx *ctx, const vc_csr *g, uint32_t k, int *yes,
                    uint32_t *cover, uint32_t *cover_len);
+
+/*
+ * A batch of independent graphs packed into one offsets buffer and one cols
+ * buffer.  Instance i is the CSR (as for vc_csr) with
+ *   offsets[offs_base[i] .. offs_base[i] + n[i]]   (offsets[offs_base[i]] = 0,
+ *                                                   the last one = nnz[i])
+ *   cols[cols_base[i] .. cols_base[i] + nnz[i] - 1] (ids local to instance i)
+ * The descriptor arrays (offs_base, cols_base, n, nnz) are host memory; with
+ * VC_CSR_DEVICE the packed offsets and cols are device memory, else host.
+ * Every instance is checked as vc_validate checks a graph.
+ */
+typedef struct {
+    uint32_t count;
+    const uint64_t *offs_base;
+    const uint64_t *cols_base;
+    const uint32_t *n;
+    const uint64_t *nnz;
+    const uint32_t *offsets;
+    const void *cols;
+    uint32_t col_bytes;
+    uint32_t flags;
+} vc_batch;
+
+/*
+ * Minimum vertex cover of every instance of a batch in one persistent
+ * search launch (the batched use of Alg. 2): workers claim instances from a
+ * device-side cursor and help on any instance through the shared worklist.
+ * The launch sequence is captured once as a hipGraph and replayed while the
+ * batch geometry and buffers stay the same (VC_OPT_NO_GRAPH: plain
+ * launches).  Outputs (host memory):
+ *   sizes[count]        MVC of each instance;
+ *   inst_status[count]  (may be NULL) VC_OK, or VC_ETIMEDOUT when the
+ *                       instance reached vc_opts.node_limit; its size and
+ *                       cover are then the best found (an upper bound);
+ *   covers, cover_offs  (both NULL, or capacity sum(n) and count+1): the
+ *                       cover of instance i, ascending local ids, is
+ *                       covers[cover_offs[i] .. cover_offs[i+1]).
+ * Returns VC_ETIMEDOUT if an instance stopped at the limit and inst_status
+ * is NULL; otherwise per-instance limits are reported only there.
+ */
+vc_status vc_min_batch(vc_ctx *ctx, const vc_batch *b, uint32_t *sizes,
+                       int32_t *inst_status, uint32_t *covers,
+                       uint64_t *cover_offs);
+
+/*
+ * Parameterized vertex cover of every instance with its own bound k[i]
+ * (host array): yes[i] = 1 iff MVC <= k[i].  An instance stops as soon as it
+ * has its answer; the others go on.  Covers as in vc_min_batch: a cover of
+ * size <= k[i] for a yes, none for a no.  An instance at the node limit has
+ * inst_status VC_ETIMEDOUT and yes = 0 (undecided).
+ */
+vc_status vc_param_batch(vc_ctx *ctx, const vc_batch *b, const uint32_t *k,
+                         int *yes, int32_t *inst_status, uint32_t *covers,
+                         uint64_t *cover_offs);
 
 /* Copy the statistics of the last completed solve. */
 vc_status vc_last_stats(vc_ctx *ctx, vc_stats *out);

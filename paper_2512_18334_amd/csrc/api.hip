@@ -14,76 +14,14 @@
 #include <new>
 #include <vector>
 
+#include "ctx.hpp"
 #include "internal.hpp"
 #include "root.hpp"
 #include "vc.h"
 
 using namespace vc;
 
-namespace {
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-};
-
-hipError_t ensure(DevBuf& b, size_t bytes) {
-    if (bytes <= b.cap && b.p) return hipSuccess;
-    if (b.p) {
-        hipError_t e = hipFree(b.p);
-        if (e) return e;
-        b.p = nullptr;
-        b.cap = 0;
-    }
-    size_t want = bytes < 256 ? 256 : bytes;
-    want = (want + 4095) & ~(size_t)4095;
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e) return e;
-    b.cap = want;
-    return hipSuccess;
-}
-
-double now_ms() {
-    using namespace std::chrono;
-    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
-
-}  // namespace
-
-struct vc_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    vc_opts opts{};
-    vc_stats last{};
-    int cus = 0;
-    size_t lds_max = 0;
-    int wall_khz = 100000;  // wall_clock64() rate
-    // input copies (host CSR) and root buffers
-    DevBuf in_off, in_col;
-    DevBuf rdeg, gdeg, gin, addf, newly, flags, newid, oldid, kdeg, koff, kcol, cover, scan_tmp,
-        ctr, hsum;
-    // search buffers
-    DevBuf stacks, wl_slots, wl_seq, ctl, reg, bitmaps, arena;
-    hipEvent_t ev[6] = {};
-};
-
-namespace {
-
-vc_status hip_status(hipError_t e) {
-    if (e == hipErrorOutOfMemory) return VC_ENOMEM;
-    return VC_EDEVICE;
-}
-
-#define HIPCHK(x)                                                                 \
-    do {                                                                          \
-        hipError_t _e = (x);                                                      \
-        if (_e != hipSuccess) {                                                   \
-            if (getenv("VC_DEBUG"))                                               \
-                fprintf(stderr, "libvc: %s failed: %s\n", #x, hipGetErrorString(_e)); \
-            return hip_status(_e);                                                \
-        }                                                                         \
-    } while (0)
+namespace vc {
 
 // Exact host-side check of a host CSR against the rules stated in vc.h.
 vc_status validate_host(const vc_csr* g) {
@@ -122,6 +60,41 @@ vc_status check_args(const vc_csr* g) {
     if (g->nnz && !g->cols) return VC_EINVAL;
     return VC_OK;
 }
+
+// Workers and LDS layout of a search over degree arrays of n_pad entries:
+// the caller's worker count, else one per CU; the LDS graph cache gets the
+// caller's size, else the most that fits the workers per CU (at most 16K
+// words).
+vc_status plan_workers(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* lp,
+                       uint32_t* gwords_out, uint32_t* workers_out) {
+    const uint32_t cus = (uint32_t)(c->cus > 0 ? c->cus : 1);
+    uint32_t workers = c->opts.workers ? c->opts.workers : cus;
+    const uint32_t base_lds = lds_plan(n_pad, deg_bytes, 0).bytes;
+    uint32_t gwords = c->opts.gcache_words;
+    if (!gwords) {
+        const uint32_t cu_lds = (uint32_t)(c->lds_max < 163840 ? c->lds_max : 163840);
+        for (uint32_t per = (workers + cus - 1u) / cus; per >= 1; --per) {
+            const uint32_t share = cu_lds / per;
+            if (share > base_lds + 4096u) {
+                gwords = std::min<uint32_t>(16384u, (share - base_lds - 64u) / 4u);
+                break;
+            }
+        }
+    }
+    *lp = lds_plan(n_pad, deg_bytes, gwords);
+    if (lp->bytes > c->lds_max) return VC_ERANGE;
+    int bpc = 0;
+    HIPCHK(search_occupancy(deg_bytes, lp->bytes, &bpc));
+    if (bpc < 1) return VC_ERANGE;
+    if (workers > (uint32_t)bpc * cus) workers = (uint32_t)bpc * cus;
+    *gwords_out = gwords;
+    *workers_out = workers;
+    return VC_OK;
+}
+
+}  // namespace vc
+
+namespace {
 
 vc_status device_validate(vc_ctx* c, const RootGraph& rg) {
     HIPCHK(ensure(c->ctr, CTR_COUNT * 4));
@@ -328,30 +301,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         const uint32_t deg_bytes = dmax <= 254u ? 1u : (dmax <= 65534u ? 2u : 4u);
         stv.deg_bytes = deg_bytes;
         const uint32_t n_pad = (np + 63u) & ~63u;
-        // LDS graph cache: the caller's size, else the most that keeps three
-        // workers per CU (two, one as the graph grows), at most 16K words
-        const uint32_t base_lds = lds_plan(n_pad, deg_bytes, 0).bytes;
-        uint32_t gwords = c->opts.gcache_words;
-        if (!gwords) {
-            const uint32_t cu_lds = (uint32_t)(c->lds_max < 163840 ? c->lds_max : 163840);
-            for (uint32_t per = 3; per >= 1; --per) {
-                const uint32_t share = cu_lds / per;
-                if (share > base_lds + 4096u) {
-                    gwords = std::min<uint32_t>(16384u, (share - base_lds - 64u) / 4u);
-                    break;
-                }
-            }
-        }
-        const LdsPlan lp = lds_plan(n_pad, deg_bytes, gwords);
-        if (lp.bytes > c->lds_max) return VC_ERANGE;
-        int bpc = 0;
-        HIPCHK(search_occupancy(deg_bytes, lp.bytes, &bpc));
-        if (bpc < 1) return VC_ERANGE;
-        // one worker per CU by default: the waves of a CU share its LDS and
-        // issue slots, and more workers than the tree keeps busy only add
-        // donation and polling traffic
-        uint32_t workers = c->opts.workers ? c->opts.workers : (uint32_t)c->cus;
-        if (workers > (uint32_t)(bpc * c->cus)) workers = (uint32_t)(bpc * c->cus);
+        LdsPlan lp;
+        uint32_t gwords = 0, workers = 0;
+        st = plan_workers(c, n_pad, deg_bytes, &lp, &gwords, &workers);
+        if (st) return st;
         const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes + 16u;
         uint32_t depth = std::min<uint32_t>(np, (uint32_t)kbest0) + np / 4u + 16u;
         const uint64_t budget = c->opts.hbm_budget ? c->opts.hbm_budget : (48ull << 30);
@@ -412,6 +365,8 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         a.flags = c->opts.flags;
         a.donate_slack = c->opts.donate_slack;
         a.node_limit = c->opts.node_limit;
+        a.n_roots = 1;  // one root scope (entry 0); no instance claims
+        a.batch = 0;
         a.watchdog_ticks = (uint64_t)c->wall_khz * (c->opts.watchdog_ms ? c->opts.watchdog_ms : 120000u);
 
         HIPCHK(launch_search_init(a, kbest0, deg_bytes, b.kdeg, s));
@@ -570,7 +525,11 @@ vc_status vc_ctx_destroy(vc_ctx* c) {
     DevBuf* bufs[] = {&c->in_off, &c->in_col, &c->rdeg, &c->gdeg, &c->gin, &c->addf,
                       &c->newly, &c->flags, &c->newid, &c->oldid, &c->kdeg, &c->koff,
                       &c->kcol, &c->cover, &c->scan_tmp, &c->ctr, &c->hsum, &c->stacks,
-                      &c->wl_slots, &c->wl_seq, &c->ctl, &c->reg, &c->bitmaps, &c->arena};
+                      &c->wl_slots, &c->wl_seq, &c->ctl, &c->reg, &c->bitmaps, &c->arena,
+                      &c->b_n, &c->b_nnz, &c->b_ob, &c->b_cb, &c->b_gat, &c->b_rbase,
+                      &c->b_cbase, &c->b_k, &c->b_state, &c->b_nodes, &c->b_bad, &c->b_hs,
+                      &c->b_cnt, &c->b_cov};
+    if (c->batch_exec) hipGraphExecDestroy(c->batch_exec);
     for (DevBuf* b : bufs)
         if (b->p) hipFree(b->p);
     for (auto& e : c->ev)

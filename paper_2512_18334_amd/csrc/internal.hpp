@@ -22,7 +22,8 @@ struct SlotHdr {
     uint32_t nlive;    // live vertices when stored (diagnostic)
     uint32_t stamp;    // worklist position the slot was published for (0 on stacks)
     int32_t view;      // registry entry whose graph the degree array indexes
-    uint32_t pad[2];
+    uint32_t inst;     // instance the node belongs to (batches; 0 otherwise)
+    uint32_t pad;
 };
 static_assert(sizeof(SlotHdr) == 32, "slot header is 32 bytes");
 
@@ -73,6 +74,8 @@ struct Ctl {
     int _p4[29];
     uint64_t arena_next;  // words of the graph arena in use
     uint64_t _p6[15];
+    uint32_t inst_next;   // batches: next instance to claim
+    uint32_t _p8[31];
     uint64_t nodes;   // statistics
     uint64_t comp_branches;
     uint64_t components;
@@ -90,6 +93,13 @@ struct Ctl {
     uint64_t _p7[8];
 };
 enum { CYC_FETCH = 0, CYC_REDUCE, CYC_COMPONENTS, CYC_BRANCH, CYC_COMPLETE, CYC_IDLE };
+
+// Per-instance state bits of a batch (SearchArgs::inst_state)
+enum : int {
+    INST_STOP = 1,    // answered (PVC yes) or over its node limit: drop its nodes
+    INST_LIMIT = 2,   // the node limit was reached
+    INST_FIN = 4,     // no node of the instance is left
+};
 
 struct SearchArgs {
     uint32_t n;           // vertices of the induced subgraph (root view)
@@ -119,6 +129,16 @@ struct SearchArgs {
     uint32_t strong_fences;  // 1: agent-scope release/acquire fences as well
     uint64_t node_limit;  // 0: none
     uint64_t watchdog_ticks;  // idle wait limit in wall_clock64() ticks
+    // Batches: registry entries 0 .. n_roots-1 are the instances' root
+    // scopes, each with its own graph (CSR in the arena, ids local to the
+    // instance).  Workers claim instances through Ctl::inst_next.  A
+    // single solve has one root (entry 0) whose view is off/col above.
+    uint32_t n_roots;
+    uint32_t batch;           // 1: the roots are claimed instances
+    int* inst_state;          // [n_roots] INST_* bits
+    uint64_t* inst_nodes;     // [n_roots] tree nodes per instance
+    const int* inst_k;        // [n_roots] PVC bound per instance (batch PVC)
+    uint64_t inst_node_limit; // per instance, 0: none
 };
 
 // LDS layout of one worker: degree array, live list L, scratch lists Q and
@@ -149,5 +169,26 @@ hipError_t launch_search(const SearchArgs& a, uint32_t deg_bytes, uint32_t worke
 hipError_t search_occupancy(uint32_t deg_bytes, uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_search_init(const SearchArgs& a, int best0, uint32_t deg_bytes,
                               const uint32_t* kdeg, hipStream_t st);
+
+// Batch set-up: instance graphs copied into the arena, root entries,
+// initial covers, per-instance state and the control block.
+struct BatchDesc {
+    uint32_t count;
+    const uint32_t* n;          // [count]
+    const uint64_t* nnz;        // [count]
+    const uint64_t* offs_base;  // [count]
+    const uint64_t* cols_base;  // [count]
+    const uint64_t* g_at;       // [count] arena word offset of each instance graph
+    const uint32_t* offsets;    // packed input
+    const void* cols;
+    uint32_t col_bytes;
+    uint64_t inst_words;        // arena words taken by the instance graphs
+};
+hipError_t launch_batch_pack(const SearchArgs& a, const BatchDesc& d, hipStream_t st);
+hipError_t launch_batch_init(const SearchArgs& a, const BatchDesc& d, hipStream_t st);
+// cover lists: instance i's root bitmap as ascending ids at out + cbase[i],
+// the count in cnt[i]
+hipError_t launch_batch_cover(const SearchArgs& a, const BatchDesc& d, const uint64_t* cbase,
+                              uint32_t* out, uint32_t* cnt, hipStream_t st);
 
 }  // namespace vc

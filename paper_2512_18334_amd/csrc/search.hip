@@ -102,8 +102,10 @@ struct Worker {
     uint64_t cyc[6];
     uint64_t t_mark;
     uint64_t b_nodes, b_reg;  // algorithmic bytes written (node slots; registry)
+    uint32_t inst;            // instance of the current node (batches)
+    uint64_t inst_cnt;        // its nodes not yet added to inst_nodes
 
-    __device__ Worker(const SearchArgs& a, uint8_t* lds) : A(a) {
+    __device__ __forceinline__ Worker(const SearchArgs& a, uint8_t* lds) : A(a) {
         deg = reinterpret_cast<D*>(lds);
         L = reinterpret_cast<uint32_t*>(lds + a.lds_L);
         Q = reinterpret_cast<uint32_t*>(lds + a.lds_Q);
@@ -114,6 +116,8 @@ struct Worker {
         stack = a.stacks + (size_t)blockIdx.x * a.stack_depth * a.slot_bytes;
         bot = top = 0;
         b_nodes = b_reg = 0;
+        inst = 0;
+        inst_cnt = 0;
         for (int i = 0; i < 6; ++i) cyc[i] = 0;
         t_mark = clock64();
         since_check = 0;
@@ -133,16 +137,16 @@ struct Worker {
 
     // ------------------------------------------------------- registry access
 
-    __device__ int reg_field(const int* p) {
+    __device__ __forceinline__ int reg_field(const int* p) {
         int b = 0;
         if (lane() == 0) b = ld_relaxed(p);
         return uni(b);
     }
-    __device__ int scope_best(int e) { return reg_field(&A.reg[e].best); }
-    __device__ uint32_t* bitmap(int e) { return A.bitmaps + (size_t)e * A.bm_words; }
+    __device__ __forceinline__ int scope_best(int e) { return reg_field(&A.reg[e].best); }
+    __device__ __forceinline__ uint32_t* bitmap(int e) { return A.bitmaps + (size_t)e * A.bm_words; }
 
     // registry entries are only ever accessed with coherent atomics
-    __device__ void init_entry(int e, int best_or_sum, int live, int up, int cover_size,
+    __device__ __forceinline__ void init_entry(int e, int best_or_sum, int live, int up, int cover_size,
                                int nchild, int size, int v, int vnn, uint32_t g_at, int g_nnz) {
         RegEntry* r = &A.reg[e];
         st_relaxed(&r->best, best_or_sum);
@@ -165,9 +169,9 @@ struct Worker {
     // Make entry v's graph the current view: the root's induced subgraph is
     // read from HBM directly; a component's own subgraph is copied from the
     // arena into the LDS graph cache.
-    __device__ void load_view(int v) {
+    __device__ __forceinline__ void load_view(int v) {
         if (v == view) return;
-        if (v == 0) {
+        if (v == 0 && !A.batch) {
             voff = A.off;
             vcol = A.col;
             vn = A.n;
@@ -177,10 +181,16 @@ struct Worker {
             const uint32_t nnz = (uint32_t)reg_field(&A.reg[v].g_nnz);
             const uint32_t* src = A.arena + g_at;
             const uint32_t words = n + 1u + nnz;
-            for (uint32_t i = lane(); i < words; i += 64) G[i] = ld_coh(&src[i]);
-            wave_sync();
-            voff = G;
-            vcol = G + n + 1;
+            if (words <= A.gcache_words) {
+                for (uint32_t i = lane(); i < words; i += 64) G[i] = ld_coh(&src[i]);
+                wave_sync();
+                voff = G;
+            } else {
+                // an instance graph of a batch too large for the cache: read
+                // in place (written before the search started)
+                voff = src;
+            }
+            vcol = voff + n + 1;
             vn = n;
         }
         vpad = (vn + 63u) & ~63u;
@@ -188,9 +198,14 @@ struct Worker {
         view = v;
     }
 
+    // vertex count of view vw
+    __device__ __forceinline__ uint32_t view_n(int vw) {
+        return (vw == 0 && !A.batch) ? A.n : (uint32_t)reg_field(&A.reg[vw].vn);
+    }
+
     // ------------------------------------------------------- live list
 
-    __device__ void build_live() {
+    __device__ __forceinline__ void build_live() {
         const uint32_t l = lane();
         uint32_t cnt = 0;
         uint64_t sum = 0, k = 0;
@@ -213,7 +228,7 @@ struct Worker {
         wave_sync();
     }
 
-    __device__ void recompact() {
+    __device__ __forceinline__ void recompact() {
         const uint32_t l = lane();
         uint32_t cnt = 0;
         uint64_t sum = 0, k = 0;
@@ -239,7 +254,7 @@ struct Worker {
 
     // Put the vertices of list[0..cnt) into the cover (duplicates allowed):
     // mark them, then remove their edges.  Returns how many were new.
-    __device__ uint32_t take_list(uint32_t* list, uint32_t cnt) {
+    __device__ __forceinline__ uint32_t take_list(uint32_t* list, uint32_t cnt) {
         const uint32_t l = lane();
         uint32_t nn = 0;
         for (uint32_t base = 0; base < cnt; base += 64) {
@@ -261,7 +276,7 @@ struct Worker {
 
     // ------------------------------------------------------- reduce
 
-    __device__ bool adjacent(uint32_t u, uint32_t w) {
+    __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t w) {
         uint32_t a = u, b = w;
         if (voff[w + 1] - voff[w] < voff[u + 1] - voff[u]) {
             a = w;
@@ -279,7 +294,7 @@ struct Worker {
     // neighbour also has degree one defers to the lower id, and of the
     // degree-two vertices of one triangle only the lowest id fires, so the
     // joint effect equals some sequential order.  Returns false if pruned.
-    __device__ bool reduce() {
+    __device__ __forceinline__ bool reduce() {
         const uint32_t l = lane();
         bool changed_any = false;
         for (;;) {
@@ -354,7 +369,7 @@ struct Worker {
     // until all live vertices are visited (Sec. III-B).  Q receives the
     // vertices grouped by component, R[0..nc] the group boundaries, PB the
     // parity of each vertex's BFS level.  Returns nc.
-    __device__ uint32_t find_components() {
+    __device__ __forceinline__ uint32_t find_components() {
         const uint32_t l = lane();
         for (uint32_t i = l; i < vbw; i += 64) {
             VB[i] = 0u;
@@ -416,7 +431,7 @@ struct Worker {
     // Write a slot: header, degree array src (npad elements of view vw) and
     // trailer.  Worklist slots (coh) use coherent stores; private stack
     // slots are written and read by this worker only and use plain stores.
-    __device__ void write_slot(uint8_t* slot, int ss, int sc, uint32_t bv, uint32_t live,
+    __device__ __forceinline__ void write_slot(uint8_t* slot, int ss, int sc, uint32_t bv, uint32_t live,
                                uint32_t stamp, const D* src, int vw, uint32_t npad, bool coh) {
         const uint32_t l = lane();
         uint32_t hw = 0;  // header word l (8 words)
@@ -426,6 +441,7 @@ struct Worker {
         if (l == 3) hw = live;
         if (l == 4) hw = stamp;
         if (l == 5) hw = (uint32_t)vw;
+        if (l == 6) hw = inst;
         uint32_t* h = reinterpret_cast<uint32_t*>(slot);
         uint32_t* tr = reinterpret_cast<uint32_t*>(slot + A.slot_bytes - 16u);
         const uint32_t nw = (npad * (uint32_t)sizeof(D)) / 8u;
@@ -444,13 +460,14 @@ struct Worker {
     }
 
     // copy a private-stack node into LDS; returns its pending branch vertex
-    __device__ uint32_t copy_slot(const uint8_t* slot) {
+    __device__ __forceinline__ uint32_t copy_slot(const uint8_t* slot) {
         const uint32_t l = lane();
         const uint32_t* h = reinterpret_cast<const uint32_t*>(slot);
         uint32_t hw = l < 8 ? h[l] : 0u;
         s = uni((int)shfl(hw, 0));
         scope = uni((int)shfl(hw, 1));
         const uint32_t bv = uni(shfl(hw, 2));
+        set_inst(uni(shfl(hw, 6)));
         load_view(uni((int)shfl(hw, 5)));
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(slot + sizeof(SlotHdr));
         uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
@@ -460,37 +477,47 @@ struct Worker {
         return bv;
     }
 
-    // copy a worklist node into LDS with coherent loads; returns the stamps
-    // (header, trailer) through st0/st1 and the pending branch vertex
-    __device__ uint32_t copy_slot_coh(const uint8_t* slot, uint32_t& st0, uint32_t& st1) {
+    // Copy the worklist node published for position `want` into LDS with
+    // coherent loads.  Returns false, having changed nothing, when the
+    // header or trailer still carries another stamp (an old copy of the
+    // slot) or names an entry out of range; the pending branch vertex goes
+    // to bv.
+    __device__ __forceinline__ bool copy_slot_coh(const uint8_t* slot, uint32_t want, uint32_t& bv) {
         const uint32_t l = lane();
         const uint32_t* h = reinterpret_cast<const uint32_t*>(slot);
         const uint32_t* tr = reinterpret_cast<const uint32_t*>(slot + A.slot_bytes - 16u);
         uint32_t hw = l < 8 ? ld_coh(&h[l]) : 0u;
         uint32_t t0 = l == 0 ? ld_coh(&tr[0]) : 0u;
+        const uint32_t st0 = uni(shfl(hw, 4));
+        const uint32_t st1 = uni(shfl(t0, 0));
+        const uint32_t sc = uni(shfl(hw, 1));
+        const uint32_t vw = uni(shfl(hw, 5));
+        const uint32_t ins = uni(shfl(hw, 6));
+        if (st0 != want || st1 != want || sc >= A.reg_cap || vw >= A.reg_cap ||
+            (A.batch && ins >= A.n_roots))
+            return false;
         s = uni((int)shfl(hw, 0));
-        scope = uni((int)shfl(hw, 1));
-        const uint32_t bv = uni(shfl(hw, 2));
-        st0 = uni(shfl(hw, 4));
-        st1 = uni(shfl(t0, 0));
-        load_view(uni((int)shfl(hw, 5)));
+        scope = (int)sc;
+        bv = uni(shfl(hw, 2));
+        set_inst(ins);
+        load_view((int)vw);
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(slot + sizeof(SlotHdr));
         uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
         const uint32_t nw = (vpad * (uint32_t)sizeof(D)) / 8u;
         for (uint32_t i = l; i < nw; i += 64) d8[i] = ld_coh64(&s8[i]);
         wave_sync();
-        return bv;
+        return true;
     }
 
     // start on a node copied into LDS: live list, then the pending N(v)
-    __device__ void begin_node(uint32_t bv) {
+    __device__ __forceinline__ void begin_node(uint32_t bv) {
         build_live();
         known_connected = false;
         if (bv != NONE) take_neighbours(bv);
     }
 
     // the N(v) branch: every live neighbour of v goes into the cover
-    __device__ void take_neighbours(uint32_t v) {
+    __device__ __forceinline__ void take_neighbours(uint32_t v) {
         const uint32_t l = lane();
         uint32_t cnt = 0;
         const uint32_t r0 = voff[v], r1 = voff[v + 1];
@@ -509,12 +536,12 @@ struct Worker {
 
     // ------------------------------------------------------- worklist
 
-    __device__ void publish_order() {
+    __device__ __forceinline__ void publish_order() {
         if (A.strong_fences) fence_release();
         order_point();
     }
 
-    __device__ bool hungry(uint32_t live) {
+    __device__ __forceinline__ bool hungry(uint32_t live) {
         if (A.flags & VC_OPT_NO_LOAD_BALANCE) return false;
         if (live < A.donate_min) return false;
         int idle = 0;
@@ -530,7 +557,7 @@ struct Worker {
     }
 
     // reserve a worklist position (UINT64_MAX when full)
-    __device__ uint64_t wl_reserve() {
+    __device__ __forceinline__ uint64_t wl_reserve() {
         uint64_t res = ~0ull;
         if (lane() == 0) {
             const uint64_t cap = A.wl_cap;
@@ -554,7 +581,7 @@ struct Worker {
         return uni(res);
     }
 
-    __device__ void wl_publish(uint64_t pos) {
+    __device__ __forceinline__ void wl_publish(uint64_t pos) {
         wave_sync();
         if (lane() == 0) {
             add_relaxed(&A.ctl->outstanding, 1);
@@ -566,7 +593,7 @@ struct Worker {
     }
 
     // take one node from the worklist into LDS; false if it looked empty
-    __device__ bool wl_take() {
+    __device__ __forceinline__ bool wl_take() {
         uint64_t res = ~0ull;
         if (lane() == 0) {
             const uint64_t cap = A.wl_cap;
@@ -593,16 +620,22 @@ struct Worker {
         wave_sync();
         const uint8_t* slot = A.wl_slots + (size_t)(res % A.wl_cap) * A.slot_bytes;
         const uint32_t want = (uint32_t)res;
-        uint32_t s0 = 0, s1 = 0;
-        uint32_t bv = copy_slot_coh(slot, s0, s1);
-        for (uint32_t tries = 0; !(s0 == want && s1 == want) && tries < 100000; ++tries) {
+        uint32_t bv = NONE;
+        bool fresh = copy_slot_coh(slot, want, bv);
+        for (uint32_t tries = 0; !fresh && tries < 100000; ++tries) {
             // an old copy of the slot was read: count it and read again
             if (lane() == 0) {
                 if (tries == 0) add_relaxed(&A.ctl->stale, 1ull);
                 fence_acquire();
             }
             wave_sync();
-            bv = copy_slot_coh(slot, s0, s1);
+            fresh = copy_slot_coh(slot, want, bv);
+        }
+        if (!fresh) {
+            // the published node never became visible: stop the search
+            // (the slot stays taken, so nothing else reads it)
+            fail(VC_EDEVICE);
+            return true;
         }
         if (lane() == 0) {
             order_point();
@@ -617,7 +650,7 @@ struct Worker {
     // when others are idle, else the own stack; fill(slot, stamp, coherent)
     // writes it.
     template <typename Fill>
-    __device__ bool push_node(uint32_t live, Fill&& fill) {
+    __device__ __forceinline__ bool push_node(uint32_t live, Fill&& fill) {
         ++pushes;
         // the threshold applies to what would be donated: the oldest
         // pending node when there is one, else this one
@@ -659,7 +692,7 @@ struct Worker {
     }
 
     // move the bottom entry of the private stack into worklist slot dst
-    __device__ void donate_bottom(uint8_t* dst, uint32_t stamp) {
+    __device__ __forceinline__ void donate_bottom(uint8_t* dst, uint32_t stamp) {
         const uint32_t l = lane();
         const uint8_t* src = stack + (size_t)bot * A.slot_bytes;
         const uint32_t* h = reinterpret_cast<const uint32_t*>(src);
@@ -667,7 +700,7 @@ struct Worker {
         if (l == 4) hw = stamp;
         const uint32_t vw = uni(shfl(hw, 5));
         // the entry's view decides how much of the degree array is in use
-        const uint32_t n = vw == 0u ? A.n : (uint32_t)reg_field(&A.reg[vw].vn);
+        const uint32_t n = view_n((int)vw);
         const uint32_t npad = (n + 63u) & ~63u;
         const uint32_t nw = (npad * (uint32_t)sizeof(D)) / 8u;
         uint32_t* dh = reinterpret_cast<uint32_t*>(dst);
@@ -682,7 +715,7 @@ struct Worker {
         if (bot == top) bot = top = 0;
     }
 
-    __device__ void fail(int code) {
+    __device__ __forceinline__ void fail(int code) {
         if (lane() == 0) {
             atomicCAS(&A.ctl->err, 0, code);
             st_relaxed(&A.ctl->done, 1);
@@ -691,14 +724,14 @@ struct Worker {
 
     // ------------------------------------------------------- covers
 
-    __device__ void lock(int e) {
+    __device__ __forceinline__ void lock(int e) {
         if (lane() == 0) {
             uint32_t spins = 0;
             while (!cas_acquire(&A.reg[e].lock, 0, 1)) backoff(spins);
         }
         wave_sync();
     }
-    __device__ void unlock(int e) {
+    __device__ __forceinline__ void unlock(int e) {
         wave_sync();
         if (lane() == 0) {
             publish_order();
@@ -707,7 +740,7 @@ struct Worker {
     }
 
     // the IN marks of the LDS degree array as bitmap words (current view)
-    __device__ void write_in_bitmap(uint32_t* bm) {
+    __device__ __forceinline__ void write_in_bitmap(uint32_t* bm) {
         const uint32_t l = lane();
         for (uint32_t wi = l; wi < vbw; wi += 64) {
             uint32_t bits = 0;
@@ -724,12 +757,12 @@ struct Worker {
     // state (from < 0), or is assembled from parent entry `from` and its
     // children, mapping children with their own view back through their
     // local-to-parent id maps.  Returns true if the cover was written.
-    __device__ bool improve(int e, int val, int from) {
+    __device__ __forceinline__ bool improve(int e, int val, int from) {
         int prev_cs = INF;
         const bool wrote = improve_once(e, val, from, &prev_cs);
         // PVC (Sec. III-E): a component's better cover travels up the
         // registry chain at once, so the root learns when it is within k
-        if (wrote && A.pvc && e != 0) propagate_up(e, prev_cs, val);
+        if (wrote && A.pvc && !is_root(e)) propagate_up(e, prev_cs, val);
         return wrote;
     }
 
@@ -739,7 +772,7 @@ struct Worker {
     // that total is an attained cover of the parent node and is offered to
     // the ancestor, and so on up to the root.  Partial totals can only be
     // too large (every change is a decrease), never too small.
-    __device__ void propagate_up(int c, int old, int val) {
+    __device__ __forceinline__ void propagate_up(int c, int old, int val) {
         for (;;) {
             const int p = reg_field(&A.reg[c].up);
             int u = 0;
@@ -760,14 +793,14 @@ struct Worker {
             const int a = reg_field(&A.reg[p].up);
             int prev = INF;
             if (!improve_once(a, total, p, &prev)) return;
-            if (a == 0) return;
+            if (is_root(a)) return;
             c = a;
             old = prev;
             val = total;
         }
     }
 
-    __device__ bool improve_once(int e, int val, int from, int* prev_cs) {
+    __device__ __forceinline__ bool improve_once(int e, int val, int from, int* prev_cs) {
         int old = 0;
         if (lane() == 0) old = min_relaxed(&A.reg[e].best, val);
         old = uni(old);
@@ -822,8 +855,12 @@ struct Worker {
             wrote = true;
         }
         unlock(e);
-        if (A.pvc && e == 0 && val <= A.k) {
-            if (lane() == 0) st_relaxed(&A.ctl->done, 1);
+        if (A.pvc && is_root(e) && val <= (A.batch ? A.inst_k[e] : A.k) && lane() == 0) {
+            if (A.batch)
+                __hip_atomic_fetch_or(&A.inst_state[e], INST_STOP, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            else
+                st_relaxed(&A.ctl->done, 1);
         }
         return wrote;
     }
@@ -832,8 +869,28 @@ struct Worker {
     // descendant of a component adds its Best to the parent's Sum; the last
     // component of a parent offers Sum to the ancestor's Best and finishes
     // the parent node in the ancestor's scope (Sec. III-C).
-    __device__ void complete(int e) {
-        while (e != 0) {
+    // Live-node counts are kept for every scope except the root of a single
+    // solve (its end is the end of the search).
+    __device__ __forceinline__ bool counted(int e) { return A.batch || e != 0; }
+    __device__ __forceinline__ bool is_root(int e) { return e < (int)A.n_roots; }
+
+    __device__ __forceinline__ void complete(int e) {
+        for (;;) {
+            if (is_root(e)) {
+                if (A.batch) {
+                    // the last node of an instance: its result is final
+                    int old = 0;
+                    if (lane() == 0) {
+                        old = add_relaxed(&A.reg[e].live, -1);
+                        if (old == 1) {
+                            order_point();
+                            __hip_atomic_fetch_or(&A.inst_state[e], INST_FIN, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+                return;
+            }
             int old = 0;
             if (lane() == 0) old = add_relaxed(&A.reg[e].live, -1);
             old = uni(old);
@@ -859,8 +916,30 @@ struct Worker {
 
     // ------------------------------------------------------- node handling
 
-    __device__ void count_node() {
+    // batches: add the current instance's pending node count to its total
+    // and stop the instance once it is over its limit
+    __device__ __forceinline__ void flush_inst() {
+        if (!A.batch || inst_cnt == 0) return;
+        if (lane() == 0 && inst < A.n_roots) {
+            const uint64_t tot =
+                __hip_atomic_fetch_add(&A.inst_nodes[inst], inst_cnt, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT) + inst_cnt;
+            if (A.inst_node_limit && tot > A.inst_node_limit)
+                __hip_atomic_fetch_or(&A.inst_state[inst], INST_STOP | INST_LIMIT,
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        inst_cnt = 0;
+    }
+
+    __device__ __forceinline__ void set_inst(uint32_t i) {
+        if (i == inst) return;
+        flush_inst();
+        inst = i;
+    }
+
+    __device__ __forceinline__ void count_node() {
         ++nodes;
+        if (A.batch && ++inst_cnt >= 64) flush_inst();
         if (A.node_limit && nodes - nodes_flushed >= 256) {
             uint64_t tot = 0;
             if (lane() == 0) tot = add_relaxed(&A.ctl->nodes, nodes - nodes_flushed);
@@ -870,19 +949,26 @@ struct Worker {
         }
     }
 
-    __device__ bool stop_requested(bool force) {
-        if (!force && ++since_check < 8) return false;
+    // 0: go on; 1: the whole search stops; 2: the node's instance has its
+    // answer or is over its limit, so the node is dropped
+    enum { GO = 0, STOP_ALL = 1, DROP = 2 };
+    __device__ __forceinline__ int stop_requested(bool force) {
+        if (!force && ++since_check < 8) return GO;
         since_check = 0;
-        int d = 0;
-        if (lane() == 0) d = ld_relaxed(&A.ctl->done);
-        return uni(d) != 0;
+        int d = 0, is = 0;
+        if (lane() == 0) {
+            d = ld_relaxed(&A.ctl->done);
+            if (A.batch) is = ld_relaxed(&A.inst_state[inst]);
+        }
+        if (uni(d) != 0) return STOP_ALL;
+        return (uni(is) & INST_STOP) ? DROP : GO;
     }
 
     // vertex branch on v_max: the G - N(v) child is pushed (lazily, as the
     // current state plus v), the G - v child continues here
-    __device__ bool vertex_branch() {
+    __device__ __forceinline__ bool vertex_branch() {
         const uint32_t v = ~(uint32_t)(key & 0xFFFFFFFFull);
-        if (scope != 0 && lane() == 0) add_relaxed(&A.reg[scope].live, 1);
+        if (counted(scope) && lane() == 0) add_relaxed(&A.reg[scope].live, 1);
         const int ss = s, sc = scope;
         if (!push_node(nl, [&](uint8_t* slot, uint32_t stamp, bool coh) {
                 write_slot(slot, ss, sc, v, nl, stamp, deg, view, vpad, coh);
@@ -899,7 +985,7 @@ struct Worker {
     // Classify the components found: cliques and chordless cycles are
     // solved on the spot (Sec. III-D); the others are listed in
     // R[nc+1 ..].  Returns the number of other components.
-    __device__ uint32_t settle_simple_components(uint32_t nc) {
+    __device__ __forceinline__ uint32_t settle_simple_components(uint32_t nc) {
         const uint32_t l = lane();
         uint32_t* NT = R + nc + 1;
         uint32_t nt = 0;
@@ -945,7 +1031,7 @@ struct Worker {
     // off[size+1], col[nnz] (local ids = positions in Q), l2g[size] (ids of
     // the current view).  M is an id map scratch of vn words, CUR one of
     // size words.  Returns the arena word offset, or NONE if it is full.
-    __device__ uint32_t induce_component(uint32_t a, uint32_t b, uint32_t nnz, uint32_t* M,
+    __device__ __forceinline__ uint32_t induce_component(uint32_t a, uint32_t b, uint32_t nnz, uint32_t* M,
                                          uint32_t* CUR) {
         const uint32_t l = lane();
         const uint32_t size = b - a;
@@ -1001,7 +1087,7 @@ struct Worker {
     // when the registry is full (the caller then branches on a vertex) and
     // CB_PRUNED when the scope's bound leaves no room for the components.
     enum { CB_OK = 0, CB_FULL = 1, CB_PRUNED = 2 };
-    __device__ int component_branch(uint32_t nc, uint32_t nt) {
+    __device__ __forceinline__ int component_branch(uint32_t nc, uint32_t nt) {
         const uint32_t l = lane();
         const uint32_t* NT = R + nc + 1;
         uint32_t* M = R + A.n_pad + 64u;  // id map scratch (n_pad words)
@@ -1147,32 +1233,40 @@ struct Worker {
     }
 
     // Process one node and, depth-first, its first children in place.
-    __device__ void process() {
+    // Returns true when the whole search stops.
+    __device__ __forceinline__ bool process(bool check_now) {
         bool recount = true;
         for (;;) {
             if (recount) count_node();
             recount = true;
-            if (stop_requested(false)) return;
+            const int sr = stop_requested(check_now);
+            check_now = false;
+            if (sr == STOP_ALL) return true;
+            if (sr == DROP) {
+                complete(scope);
+                charge(CYC_COMPLETE);
+                return false;
+            }
             best = scope_best(scope);
             const bool alive = reduce();
             charge(CYC_REDUCE);
             if (!alive) {
                 complete(scope);
                 charge(CYC_COMPLETE);
-                return;
+                return false;
             }
             const int64_t b = (int64_t)best - s - 1;
             const uint64_t E = e2 / 2u;
             if (b < 0 || (int64_t)E > b * b) {
                 complete(scope);
                 charge(CYC_COMPLETE);
-                return;
+                return false;
             }
             if (E == 0) {
                 improve(scope, s, -1);
                 complete(scope);
                 charge(CYC_COMPLETE);
-                return;
+                return false;
             }
             if (!(A.flags & VC_OPT_NO_COMPONENTS) && !known_connected) {
                 const uint32_t nc = find_components();
@@ -1182,13 +1276,13 @@ struct Worker {
                 if (s >= best) {
                     complete(scope);
                     charge(CYC_COMPLETE);
-                    return;
+                    return false;
                 }
                 if (nt == 0) {
                     improve(scope, s, -1);
                     complete(scope);
                     charge(CYC_COMPLETE);
-                    return;
+                    return false;
                 }
                 if (nt == 1) {
                     known_connected = true;
@@ -1203,17 +1297,17 @@ struct Worker {
                     if (cb == CB_PRUNED) {
                         complete(scope);
                         charge(CYC_COMPLETE);
-                        return;
+                        return false;
                     }
                 }
             }
             const bool ok = vertex_branch();
             charge(CYC_BRANCH);
-            if (!ok) return;
+            if (!ok) return false;
         }
     }
 
-    __device__ void flush_stats() {
+    __device__ __forceinline__ void flush_stats() {
         if (lane() == 0) {
             add_relaxed(&A.ctl->nodes, nodes - nodes_flushed);
             add_relaxed(&A.ctl->comp_branches, cbr);
@@ -1227,11 +1321,42 @@ struct Worker {
         }
     }
 
-    __device__ void run() {
+    // Batches: take the next unclaimed instance and make its root node (the
+    // whole instance graph, nothing decided yet) the current node.
+    __device__ __forceinline__ bool claim_instance() {
+        if (!A.batch) return false;
+        uint32_t got = NONE;
+        if (lane() == 0 && ld_relaxed(&A.ctl->inst_next) < A.n_roots) {
+            // count this worker as busy first, so that no idle worker sees
+            // zero outstanding work while an instance is being claimed
+            add_relaxed(&A.ctl->outstanding, 1);
+            for (;;) {
+                const uint32_t i = atomicAdd(&A.ctl->inst_next, 1u);
+                if (i >= A.n_roots) break;
+                // instances answered during set-up have no root node
+                if (ld_relaxed(&A.inst_state[i]) & INST_FIN) continue;
+                got = i;
+                break;
+            }
+            if (got == NONE) add_relaxed(&A.ctl->outstanding, -1);
+        }
+        got = uni(got);
+        if (got == NONE) return false;
+        set_inst(got);
+        load_view((int)got);
+        for (uint32_t v = lane(); v < vpad; v += 64)
+            DG::set(deg, v, v < vn ? voff[v + 1] - voff[v] : 0u);
+        wave_sync();
+        s = 0;
+        scope = (int)got;
+        begin_node(NONE);
+        return true;
+    }
+
+    __device__ __forceinline__ void run() {
         bool busy = false;
         for (;;) {
             if (top > bot) {
-                if (stop_requested(true)) break;
                 --top;
                 begin_node(copy_slot(stack + (size_t)top * A.slot_bytes));
                 if (top == bot) bot = top = 0;
@@ -1240,6 +1365,12 @@ struct Worker {
                 bot = top = 0;
                 if (busy && lane() == 0) add_relaxed(&A.ctl->outstanding, -1);
                 busy = false;
+                if (claim_instance()) {
+                    busy = true;
+                    charge(CYC_FETCH);
+                    if (process(true)) break;
+                    continue;
+                }
                 if (lane() == 0) add_relaxed(&A.ctl->idle, 1);
                 uint32_t spins = 0;
                 bool got = false, quit = false;
@@ -1291,8 +1422,9 @@ struct Worker {
                 if (quit) break;
                 busy = got;
             }
-            process();
+            if (process(true)) break;
         }
+        flush_inst();
         flush_stats();
     }
 };
@@ -1321,6 +1453,7 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         h->nlive = a.n;
         h->stamp = 0;
         h->view = 0;
+        h->inst = 0;
         *reinterpret_cast<uint32_t*>(a.wl_slots + a.slot_bytes - 16u) = 0u;
         Ctl* c = a.ctl;
         c->wl_head = 0;
@@ -1331,6 +1464,7 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         c->err = 0;
         c->reg_next = 2;  // entry 0 is the root scope; allocations are 2-aligned
         c->arena_next = 0;
+        c->inst_next = 0;
         c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
         c->stale = c->local_views = 0;
         for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
@@ -1385,6 +1519,156 @@ hipError_t launch_search_init(const SearchArgs& a, int best0, uint32_t deg_bytes
         hipLaunchKernelGGL(search_init_kernel<uint16_t>, dim3(blocks), dim3(256), 0, st, a, best0, kdeg);
     else
         hipLaunchKernelGGL(search_init_kernel<uint32_t>, dim3(blocks), dim3(256), 0, st, a, best0, kdeg);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batches
+
+// Copy every instance graph of a batch into the arena as a 32-bit CSR with
+// instance-local ids: off[n+1] then col[nnz].  One block per instance.
+__global__ void batch_pack_kernel(SearchArgs a, BatchDesc d) {
+    for (uint32_t i = blockIdx.x; i < d.count; i += gridDim.x) {
+        const uint32_t n = d.n[i];
+        const uint64_t nnz = d.nnz[i];
+        const uint32_t* so = d.offsets + d.offs_base[i];
+        uint32_t* dst = a.arena + d.g_at[i];
+        for (uint32_t v = threadIdx.x; v <= n; v += blockDim.x) dst[v] = so[v];
+        uint32_t* dc = dst + n + 1u;
+        if (d.col_bytes == 2) {
+            const uint16_t* sc = reinterpret_cast<const uint16_t*>(d.cols) + d.cols_base[i];
+            for (uint64_t e = threadIdx.x; e < nnz; e += blockDim.x) dc[e] = sc[e];
+        } else {
+            const uint32_t* sc = reinterpret_cast<const uint32_t*>(d.cols) + d.cols_base[i];
+            for (uint64_t e = threadIdx.x; e < nnz; e += blockDim.x) dc[e] = sc[e];
+        }
+    }
+}
+
+// Root entries, initial covers and state of every instance, the empty
+// worklist and the control block.  An instance's first bound is |V|-1
+// (V minus its last vertex is a cover); PVC starts from k+1 unless that
+// trivial cover already answers it.  Edgeless instances and trivial PVC
+// answers are final before the search.
+__global__ void batch_init_kernel(SearchArgs a, BatchDesc d) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = tid; i < a.wl_cap; i += stride) a.wl_seq[i] = (uint64_t)i;
+    for (uint32_t i = tid; i < d.count; i += stride) {
+        const uint32_t n = d.n[i];
+        const bool edges = d.nnz[i] != 0;
+        int best0, cs, state = 0;
+        bool all_but_last = false;
+        if (!edges) {
+            best0 = 0;
+            cs = 0;
+            state = INST_STOP | INST_FIN;
+        } else if (a.pvc && (int64_t)n - 1 <= (int64_t)a.inst_k[i]) {
+            best0 = (int)n - 1;
+            cs = best0;
+            all_but_last = true;
+            state = INST_STOP | INST_FIN;
+        } else if (a.pvc) {
+            best0 = a.inst_k[i] + 1;
+            cs = INF;
+        } else {
+            best0 = (int)n - 1;
+            cs = best0;
+            all_but_last = true;
+        }
+        RegEntry r = {};
+        r.best = best0;
+        r.live = 1;
+        r.up = -1;
+        r.lock = 0;
+        r.cover_size = cs;
+        r.nchild = 0;
+        r.size = (int)n;
+        r.view = (int)i;
+        r.vn = (int)n;
+        r.g_at = (uint32_t)d.g_at[i];
+        r.g_nnz = (int)d.nnz[i];
+        a.reg[i] = r;
+        a.inst_state[i] = state;
+        a.inst_nodes[i] = 0;
+        uint32_t* bm = a.bitmaps + (size_t)i * a.bm_words;
+        for (uint32_t w = 0; w < a.bm_words; ++w) {
+            uint32_t bits = 0;
+            if (all_but_last) {
+                const uint32_t lo = w * 32u;
+                const uint32_t m = n - 1u;  // bits lo .. m-1
+                if (m >= lo + 32u) bits = ~0u;
+                else if (m > lo) bits = (1u << (m - lo)) - 1u;
+            }
+            bm[w] = bits;
+        }
+    }
+    if (tid == 0) {
+        Ctl* c = a.ctl;
+        c->wl_head = 0;
+        c->wl_tail = 0;
+        c->outstanding = 0;
+        c->idle = 0;
+        c->done = 0;
+        c->err = 0;
+        c->reg_next = (d.count + 1u) & ~1u;
+        c->arena_next = d.inst_words;
+        c->inst_next = 0;
+        c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
+        c->stale = c->local_views = 0;
+        for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
+        c->bytes_nodes = c->bytes_registry = 0;
+    }
+}
+
+// Instance i's root bitmap as ascending vertex ids at out + cbase[i] and
+// their number in cnt[i].  One wave per instance.
+__global__ void __launch_bounds__(64) batch_cover_kernel(SearchArgs a, BatchDesc d,
+                                                         const uint64_t* cbase, uint32_t* out,
+                                                         uint32_t* cnt) {
+    const uint32_t l = lane();
+    for (uint32_t i = blockIdx.x; i < d.count; i += gridDim.x) {
+        const uint32_t n = d.n[i];
+        const uint32_t words = (n + 31u) / 32u;
+        const uint32_t* bm = a.bitmaps + (size_t)i * a.bm_words;
+        uint32_t* o = out + cbase[i];
+        uint32_t total = 0;
+        for (uint32_t w0 = 0; w0 < words; w0 += 64) {
+            const uint32_t w = w0 + l;
+            uint32_t bits = w < words ? bm[w] : 0u;
+            if (w == words - 1u && (n & 31u)) bits &= (1u << (n & 31u)) - 1u;
+            const uint32_t c = (uint32_t)__builtin_popcount(bits);
+            const uint32_t incl = wave_incl_scan(c);
+            uint32_t at = total + incl - c;
+            while (bits) {
+                const uint32_t b = (uint32_t)__builtin_ctz(bits);
+                bits &= bits - 1u;
+                o[at++] = w * 32u + b;
+            }
+            total += shfl(incl, 63);
+        }
+        if (l == 0) cnt[i] = total;
+    }
+}
+
+hipError_t launch_batch_pack(const SearchArgs& a, const BatchDesc& d, hipStream_t st) {
+    const uint32_t blocks = d.count < 4096u ? (d.count ? d.count : 1u) : 4096u;
+    hipLaunchKernelGGL(batch_pack_kernel, dim3(blocks), dim3(256), 0, st, a, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const SearchArgs& a, const BatchDesc& d, hipStream_t st) {
+    const uint32_t work = a.wl_cap > d.count ? a.wl_cap : d.count;
+    uint32_t blocks = (work + 255u) / 256u;
+    if (blocks > 1024u) blocks = 1024u;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(batch_init_kernel, dim3(blocks), dim3(256), 0, st, a, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_cover(const SearchArgs& a, const BatchDesc& d, const uint64_t* cbase,
+                              uint32_t* out, uint32_t* cnt, hipStream_t st) {
+    const uint32_t blocks = d.count < 8192u ? (d.count ? d.count : 1u) : 8192u;
+    hipLaunchKernelGGL(batch_cover_kernel, dim3(blocks), dim3(64), 0, st, a, d, cbase, out, cnt);
     return hipGetLastError();
 }
 

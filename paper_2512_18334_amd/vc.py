@@ -23,17 +23,27 @@ VC_CSR_DEVICE = 1
 VC_OPT_NO_COMPONENTS = 1
 VC_OPT_NO_LOAD_BALANCE = 2
 VC_OPT_VALIDATE_SKIP = 4
+VC_OPT_NO_GRAPH = 8
 
 CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]
 
 EXPORTS = ["vc_ctx_create", "vc_ctx_destroy", "vc_validate", "vc_min",
-           "vc_param", "vc_last_stats", "vc_status_str"]
+           "vc_param", "vc_min_batch", "vc_param_batch", "vc_last_stats",
+           "vc_status_str"]
 
 
 class vc_csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("nnz", ctypes.c_uint64),
                 ("offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p),
                 ("col_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class vc_batch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint32), ("offs_base", ctypes.c_void_p),
+                ("cols_base", ctypes.c_void_p), ("n", ctypes.c_void_p),
+                ("nnz", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("cols", ctypes.c_void_p), ("col_bytes", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
 
 
 class vc_opts(ctypes.Structure):
@@ -100,6 +110,13 @@ def load():
     lib.vc_param.restype = ctypes.c_int
     lib.vc_param.argtypes = [p, ctypes.POINTER(vc_csr), ctypes.c_uint32,
                              ctypes.POINTER(ctypes.c_int), u32p, u32p]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.vc_min_batch.restype = ctypes.c_int
+    lib.vc_min_batch.argtypes = [p, ctypes.POINTER(vc_batch), u32p, i32p, u32p, u64p]
+    lib.vc_param_batch.restype = ctypes.c_int
+    lib.vc_param_batch.argtypes = [p, ctypes.POINTER(vc_batch), u32p,
+                                   ctypes.POINTER(ctypes.c_int), i32p, u32p, u64p]
     lib.vc_last_stats.restype = ctypes.c_int
     lib.vc_last_stats.argtypes = [p, ctypes.POINTER(vc_stats)]
     lib.vc_status_str.restype = ctypes.c_char_p
@@ -150,6 +167,69 @@ def host_csr(g):
                off.ctypes.data, cols.ctypes.data if cols.size else None,
                int(cols.dtype.itemsize), 0)
     return c, (off, cols)
+
+
+@dataclass
+class Batch:
+    """Graphs packed into one offsets and one cols buffer (vc_batch).  The
+    descriptor arrays stay on the host; offsets and cols are numpy arrays,
+    or torch tensors on the device after to_device()."""
+    n: np.ndarray          # uint32 [count]
+    nnz: np.ndarray        # uint64 [count]
+    offs_base: np.ndarray  # uint64 [count]
+    cols_base: np.ndarray  # uint64 [count]
+    offsets: object        # uint32 [sum(n+1)]
+    cols: object           # uint16 or uint32 [sum(nnz)]
+    col_bytes: int
+    device: bool = False
+
+    @classmethod
+    def from_graphs(cls, graphs, col_bytes: int = 0):
+        graphs = list(graphs)
+        cb = col_bytes or (2 if all(g.n <= 65536 for g in graphs) else 4)
+        ns = np.array([g.n for g in graphs], np.uint32)
+        nnz = np.array([g.nnz for g in graphs], np.uint64)
+        ob = np.zeros(len(graphs), np.uint64)
+        cbase = np.zeros(len(graphs), np.uint64)
+        if len(graphs) > 1:
+            ob[1:] = np.cumsum(ns[:-1].astype(np.uint64) + 1)
+            cbase[1:] = np.cumsum(nnz[:-1])
+        cdt = np.uint16 if cb == 2 else np.uint32
+        offsets = (np.concatenate([np.asarray(g.offsets, np.uint32) for g in graphs])
+                   if graphs else np.zeros(1, np.uint32))
+        cols = (np.concatenate([np.asarray(g.cols).astype(cdt) for g in graphs])
+                if graphs else np.zeros(1, cdt))
+        return cls(ns, nnz, ob, cbase, offsets, cols, cb)
+
+    @property
+    def count(self) -> int:
+        return int(self.n.size)
+
+    def to_device(self, device="cuda"):
+        import torch
+        off = torch.from_numpy(self.offsets.view(np.int32)).to(device)
+        cdt = np.int16 if self.col_bytes == 2 else np.int32
+        col = torch.from_numpy(np.ascontiguousarray(self.cols).view(cdt)).to(device)
+        return Batch(self.n, self.nnz, self.offs_base, self.cols_base, off, col,
+                     self.col_bytes, True)
+
+    def c_struct(self) -> vc_batch:
+        if self.device:
+            op, cp = self.offsets.data_ptr(), self.cols.data_ptr()
+        else:
+            op, cp = self.offsets.ctypes.data, self.cols.ctypes.data
+        return vc_batch(self.count, self.offs_base.ctypes.data, self.cols_base.ctypes.data,
+                        self.n.ctypes.data, self.nnz.ctypes.data, op, cp,
+                        self.col_bytes, VC_CSR_DEVICE if self.device else 0)
+
+
+@dataclass
+class BatchResult:
+    sizes: np.ndarray | None   # MVC per instance (None for PVC)
+    yes: np.ndarray | None     # PVC answers (None for MVC)
+    status: np.ndarray         # VC_OK or VC_ETIMEDOUT per instance
+    covers: list               # ascending local ids per instance
+    stats: dict
 
 
 @dataclass
@@ -236,6 +316,60 @@ class Solver:
                              cp, ctypes.byref(clen))
         _check(st, "vc_param")
         return Result(None, bool(yes.value), cov[:clen.value].copy(), self.stats())
+
+
+    def mvc_batch(self, batch, want_cover: bool = True) -> BatchResult:
+        """vc_min_batch over a Batch (or a list of graphs, packed here)."""
+        b = _as_batch(batch)
+        c = b.c_struct()
+        cnt = b.count
+        sizes = np.zeros(max(cnt, 1), np.uint32)
+        status = np.zeros(max(cnt, 1), np.int32)
+        flat = np.zeros(max(int(b.n.sum()), 1), np.uint32)
+        offs = np.zeros(cnt + 1, np.uint64)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        st = load().vc_min_batch(
+            self._h, ctypes.byref(c), sizes.ctypes.data_as(u32p),
+            status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            flat.ctypes.data_as(u32p) if want_cover else None,
+            offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) if want_cover else None)
+        _check(st, "vc_min_batch")
+        covers = _split_covers(flat, offs, cnt) if want_cover else []
+        return BatchResult(sizes[:cnt].copy(), None, status[:cnt].copy(), covers, self.stats())
+
+
+    def pvc_batch(self, batch, ks, want_cover: bool = True) -> BatchResult:
+        """vc_param_batch with one bound per instance."""
+        b = _as_batch(batch)
+        c = b.c_struct()
+        cnt = b.count
+        kk = np.ascontiguousarray(np.asarray(ks, np.uint32).reshape(-1))
+        if kk.size != cnt:
+            raise ValueError("one k per instance")
+        yes = np.zeros(max(cnt, 1), np.int32)
+        status = np.zeros(max(cnt, 1), np.int32)
+        flat = np.zeros(max(int(b.n.sum()), 1), np.uint32)
+        offs = np.zeros(cnt + 1, np.uint64)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        st = load().vc_param_batch(
+            self._h, ctypes.byref(c), kk.ctypes.data_as(u32p),
+            yes.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            flat.ctypes.data_as(u32p) if want_cover else None,
+            offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) if want_cover else None)
+        _check(st, "vc_param_batch")
+        covers = _split_covers(flat, offs, cnt) if want_cover else []
+        return BatchResult(None, yes[:cnt].astype(bool), status[:cnt].copy(), covers,
+                           self.stats())
+
+def _as_batch(b):
+    return b if isinstance(b, Batch) else Batch.from_graphs(b)
+
+
+def _split_covers(flat, offs, count):
+    return [flat[offs[i]:offs[i + 1]].copy() for i in range(count)]
+
+
 
 
 def validate_host(g) -> int:

@@ -26,7 +26,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ["vc_ctx_create", "vc_ctx_destroy", "vc_min", "vc_param",
-              "vc_validate", "vc_last_stats", "vc_status_str"]:
+              "vc_min_batch", "vc_param_batch", "vc_validate", "vc_last_stats",
+              "vc_status_str"]:
         assert f in names
 
 
@@ -46,6 +47,7 @@ def test_struct_layout_matches_header(tmp_path, libvc):
         "vc_csr": [f for f, _ in vc.vc_csr._fields_],
         "vc_opts": [f for f, _ in vc.vc_opts._fields_],
         "vc_stats": [f for f, _ in vc.vc_stats._fields_],
+        "vc_batch": [f for f, _ in vc.vc_batch._fields_],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vc.h"',
              "int main(void) {"]
@@ -61,7 +63,7 @@ def test_struct_layout_matches_header(tmp_path, libvc):
     got = dict(l.split() for l in subprocess.run(
         [str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
     for s, cls in [("vc_csr", vc.vc_csr), ("vc_opts", vc.vc_opts),
-                   ("vc_stats", vc.vc_stats)]:
+                   ("vc_stats", vc.vc_stats), ("vc_batch", vc.vc_batch)]:
         assert int(got[s]) == ctypes.sizeof(cls), s
         for f, _ in cls._fields_:
             assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
@@ -113,3 +115,28 @@ def test_host_validation_rejects_bad_widths(libvc):
     assert libvc.vc_validate(None, ctypes.byref(c)) == vc.VC_EINVAL
     big = vc.vc_csr(70000, 0, keep[0].ctypes.data, None, 2, 0)
     assert libvc.vc_validate(None, ctypes.byref(big)) == vc.VC_EINVAL
+
+
+def test_batch_entry_points_reject_missing_context(libvc):
+    b = vc.Batch.from_graphs([gg.petersen(), gg.fig1_tree()])
+    c = b.c_struct()
+    sizes = np.zeros(2, np.uint32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    assert libvc.vc_min_batch(None, ctypes.byref(c), sizes.ctypes.data_as(u32p),
+                              None, None, None) == vc.VC_EINVAL
+    k = np.array([6, 3], np.uint32)
+    yes = np.zeros(2, np.int32)
+    assert libvc.vc_param_batch(None, ctypes.byref(c), k.ctypes.data_as(u32p),
+                                yes.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                None, None, None) == vc.VC_EINVAL
+
+
+def test_batch_packing_layout():
+    gs = [gg.petersen(), gg.from_edges(0, [], []), gg.fig1_tree(), gg.cycle(5)]
+    b = vc.Batch.from_graphs(gs)
+    assert b.count == 4 and b.col_bytes == 2
+    for i, g in enumerate(gs):
+        ob, cb = int(b.offs_base[i]), int(b.cols_base[i])
+        assert np.array_equal(b.offsets[ob:ob + g.n + 1], g.offsets)
+        assert int(b.offsets[ob]) == 0 and int(b.offsets[ob + g.n]) == g.nnz
+        assert np.array_equal(b.cols[cb:cb + g.nnz], np.asarray(g.cols))
