@@ -353,6 +353,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         a.lds_R = lp.R;
         a.lds_VB = lp.VB;
         a.lds_PB = lp.PB;
+        a.lds_MK = lp.MK;
         a.lds_G = lp.G;
         a.lds_bytes = lp.bytes;
         a.gcache_words = gwords;

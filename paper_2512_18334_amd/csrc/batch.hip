@@ -319,6 +319,7 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     a.lds_R = lp.R;
     a.lds_VB = lp.VB;
     a.lds_PB = lp.PB;
+    a.lds_MK = lp.MK;
     a.lds_G = lp.G;
     a.lds_bytes = lp.bytes;
     a.pvc = pvc;

@@ -83,8 +83,17 @@ __device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// all lanes agree (wave is the whole workgroup: a barrier is one wave sync)
-__device__ __forceinline__ void wave_sync() { __syncthreads(); }
+// Order LDS traffic between the lanes of one wave (a worker is one wave and
+// the whole workgroup).  The LDS executes a wave's instructions in issue
+// order, so no wait is needed in hardware; the wavefront-scope fences keep
+// the compiler from moving LDS accesses across this point or forwarding a
+// lane's own store to a later load that another lane may have overwritten.
+// Unlike a workgroup barrier, it does not wait for global memory traffic.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ------------------------------------------------------------ atomics
 // Agent scope = the whole GPU (all XCDs).  Relaxed operations are used for
@@ -167,7 +176,13 @@ __device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
 // point between writing a payload and publishing it (and between the two
 // halves of a registry update), without the whole-cache write-back and
 // invalidate an agent-scope fence costs on a multi-XCD part.
-__device__ __forceinline__ void order_point() { __builtin_amdgcn_s_waitcnt(0); }
+__device__ __forceinline__ void order_point() {
+    // compiler fences on both sides: no memory access of any lane moves
+    // across the wait
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 // idle wait: short sleeps first, then up to 8 x 63 x 64 clocks per round
 __device__ __forceinline__ void backoff(uint32_t& spins) {

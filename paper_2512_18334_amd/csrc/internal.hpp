@@ -120,7 +120,7 @@ struct SearchArgs {
     uint32_t* arena;      // graph arena (local views)
     uint64_t arena_words;
     uint32_t gcache_words;  // LDS graph cache capacity (words)
-    uint32_t lds_L, lds_Q, lds_R, lds_VB, lds_PB, lds_G, lds_bytes;
+    uint32_t lds_L, lds_Q, lds_R, lds_VB, lds_PB, lds_MK, lds_G, lds_bytes;
     int pvc;              // 1: parameterized (stop once the root is <= k)
     int k;
     uint32_t flags;       // VC_OPT_* ablation switches
@@ -142,9 +142,10 @@ struct SearchArgs {
 };
 
 // LDS layout of one worker: degree array, live list L, scratch lists Q and
-// R (R doubles as an id map of n_pad words), two bitmaps, graph cache.
+// R (R doubles as an id map of n_pad words), two bitmaps, 64 words of row
+// markers for the row expansion, graph cache.
 struct LdsPlan {
-    uint32_t L, Q, R, VB, PB, G, bytes;
+    uint32_t L, Q, R, VB, PB, MK, G, bytes;
 };
 inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd, uint32_t gcache_words) {
     LdsPlan p;
@@ -156,6 +157,7 @@ inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd, uint32_t gcache_words) {
     uint32_t bw = (n_pad + 31u) / 32u;
     p.VB = at; at += 4u * bw;
     p.PB = at; at += 4u * bw;
+    p.MK = at; at += 4u * 64u;
     p.G = at; at += 4u * gcache_words;
     p.bytes = (at + 15u) & ~15u;
     return p;

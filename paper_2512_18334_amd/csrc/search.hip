@@ -38,38 +38,46 @@ __device__ __forceinline__ uint64_t uni(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Visit every CSR entry of the rows of list[0..cnt): lane t of a 64-wide
-// chunk of the flattened rows finds its row by a binary search over the
-// lanes' exclusive prefix sums (load-balanced expansion).  f(ok, v, w) is
-// called by all lanes in lock-step; ok is false on padding lanes.
-template <typename F>
-__device__ __forceinline__ void for_rows(const uint32_t* off, const uint32_t* col,
-                                         const uint32_t* list, uint32_t cnt, F&& f) {
+// Visit every CSR entry of the rows of list[0..cnt) (load-balanced
+// expansion): the rows of 64 list entries are laid end to end by a prefix
+// sum of their lengths and cut into 64-entry chunks.  In a chunk, every row
+// that starts there marks its lane at its start position in MK (64 words
+// of LDS), and an inclusive max-scan over the marks gives each entry its
+// row; entries before the first start continue the previous chunk's last
+// row.  f(ok, v, w) is called by all lanes in lock-step; ok is false on
+// padding lanes.
+template <typename Off, typename Col, typename F>
+__device__ __forceinline__ void for_rows(Off&& off, Col&& col, const uint32_t* list,
+                                         uint32_t cnt, uint32_t* MK, F&& f) {
     const uint32_t l = lane();
     for (uint32_t base = 0; base < cnt; base += 64) {
         uint32_t i = base + l;
         uint32_t v = 0, r0 = 0, len = 0;
         if (i < cnt) {
             v = list[i];
-            r0 = off[v];
-            len = off[v + 1] - r0;
+            r0 = off(v);
+            len = off(v + 1) - r0;
         }
-        uint32_t incl = wave_incl_scan(len);
-        uint32_t excl = incl - len;
-        uint32_t total = shfl(incl, 63);
+        const uint32_t incl = wave_incl_scan(len);
+        const uint32_t excl = incl - len;
+        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        const uint32_t delta = r0 - excl;  // CSR position of flat entry t is t + delta
+        uint32_t carry = 0;                // (lane + 1) of the row running into the chunk
         for (uint32_t t0 = 0; t0 < total; t0 += 64) {
-            uint32_t t = t0 + l;
-            uint32_t j = 0;
-#pragma unroll
-            for (uint32_t step = 32; step >= 1; step >>= 1) {
-                uint32_t c = j + step;
-                uint32_t ec = shfl(excl, c & 63u);
-                if (c < 64u && ec <= t) j = c;
-            }
-            uint32_t vj = shfl(v, j);
-            uint32_t e = shfl(r0, j) + (t - shfl(excl, j));
-            bool ok = t < total;
-            uint32_t w = ok ? col[e] : 0u;
+            wave_sync();  // the previous chunk's reads of MK are done
+            MK[l] = 0u;
+            if (len && excl >= t0 && excl - t0 < 64u) MK[excl - t0] = l + 1u;
+            wave_sync();  // other lanes' marks are visible
+            uint32_t own = MK[l];
+            VC_DPP_SCAN(own, op_max, 0u);
+            own = own > carry ? own : carry;
+            carry = __builtin_amdgcn_readlane(own, 63);
+            const uint32_t j = own - 1u;
+            const uint32_t t = t0 + l;
+            const bool ok = t < total;
+            const uint32_t vj = shfl(v, j);
+            const uint32_t e = t + shfl(delta, j);
+            const uint32_t w = ok ? col(e) : 0u;
             f(ok, vj, w);
         }
     }
@@ -80,12 +88,17 @@ struct Worker {
     using DG = Deg<D>;
     SearchArgs A;
     D* deg;
-    uint32_t *L, *Q, *R, *VB, *PB, *G;
+    uint32_t *L, *Q, *R, *VB, *PB, *MK, *G;
     // current graph view
     int view;
     uint32_t vn, vpad, vbw;
-    const uint32_t* voff;
-    const uint32_t* vcol;
+    // the view's CSR: in the LDS graph cache (G, columns from GC) or, when it
+    // does not fit, in HBM (goff, gcol); every read branches on vlds, a
+    // wave-uniform flag, so LDS views are read with LDS instructions only
+    bool vlds;
+    const uint32_t* goff;
+    const uint32_t* gcol;
+    uint32_t* GC;
     // node state (wave-uniform)
     uint32_t nl;    // live vertices in L
     int s;          // |S| in scope
@@ -97,7 +110,14 @@ struct Worker {
     // worker state
     uint8_t* stack;
     uint32_t bot, top;  // private stack as a deque: pop at top, donate from bot
-    uint32_t since_check;
+    uint32_t since_poll;
+    // shared state read together in one round trip every POLL_EVERY nodes
+    // (and when a node comes from elsewhere): stop flag, the instance's
+    // state, idle workers, queued nodes and the current scope's Best.  A
+    // stale Best is only a weaker bound, never a wrong one.
+    static constexpr uint32_t POLL_EVERY = 4;
+    int c_done, c_inst_state, c_idle, c_best, c_best_scope;
+    int64_t c_queued;
     uint64_t nodes, cbr, comps, dons, pushes, lviews, nodes_flushed;
     uint64_t cyc[6];
     uint64_t t_mark;
@@ -112,6 +132,7 @@ struct Worker {
         R = reinterpret_cast<uint32_t*>(lds + a.lds_R);
         VB = reinterpret_cast<uint32_t*>(lds + a.lds_VB);
         PB = reinterpret_cast<uint32_t*>(lds + a.lds_PB);
+        MK = reinterpret_cast<uint32_t*>(lds + a.lds_MK);
         G = reinterpret_cast<uint32_t*>(lds + a.lds_G);
         stack = a.stacks + (size_t)blockIdx.x * a.stack_depth * a.slot_bytes;
         bot = top = 0;
@@ -120,12 +141,18 @@ struct Worker {
         inst_cnt = 0;
         for (int i = 0; i < 6; ++i) cyc[i] = 0;
         t_mark = clock64();
-        since_check = 0;
+        since_poll = POLL_EVERY;
+        c_done = c_inst_state = c_idle = 0;
+        c_best = INF;
+        c_best_scope = -1;
+        c_queued = 0;
         nodes = cbr = comps = dons = pushes = lviews = nodes_flushed = 0;
         known_connected = false;
         view = -1;
         vn = vpad = vbw = 0;
-        voff = vcol = nullptr;
+        vlds = false;
+        goff = gcol = nullptr;
+        GC = G;
     }
 
     // charge the shader cycles since the last mark to activity k
@@ -143,6 +170,35 @@ struct Worker {
         return uni(b);
     }
     __device__ __forceinline__ int scope_best(int e) { return reg_field(&A.reg[e].best); }
+
+    __device__ __forceinline__ void poll() {
+        int d = 0, is = 0, idl = 0, bst = 0;
+        uint64_t h = 0, t = 0;
+        if (lane() == 0) {
+            d = ld_relaxed(&A.ctl->done);
+            if (A.batch) is = ld_relaxed(&A.inst_state[inst]);
+            idl = ld_relaxed(&A.ctl->idle);
+            h = ld_relaxed(&A.ctl->wl_head);
+            t = ld_relaxed(&A.ctl->wl_tail);
+            bst = ld_relaxed(&A.reg[scope].best);
+        }
+        c_done = uni(d);
+        c_inst_state = uni(is);
+        c_idle = uni(idl);
+        c_queued = (int64_t)(uni(t) - uni(h));
+        c_best = uni(bst);
+        c_best_scope = scope;
+        since_poll = 0;
+    }
+
+    // the current scope's Best (cached; read afresh when the scope changed)
+    __device__ __forceinline__ int cur_best() {
+        if (scope != c_best_scope) {
+            c_best = scope_best(scope);
+            c_best_scope = scope;
+        }
+        return c_best;
+    }
     __device__ __forceinline__ uint32_t* bitmap(int e) { return A.bitmaps + (size_t)e * A.bm_words; }
 
     // registry entries are only ever accessed with coherent atomics
@@ -172,8 +228,9 @@ struct Worker {
     __device__ __forceinline__ void load_view(int v) {
         if (v == view) return;
         if (v == 0 && !A.batch) {
-            voff = A.off;
-            vcol = A.col;
+            vlds = false;
+            goff = A.off;
+            gcol = A.col;
             vn = A.n;
         } else {
             const uint32_t g_at = (uint32_t)reg_field(reinterpret_cast<const int*>(&A.reg[v].g_at));
@@ -184,19 +241,24 @@ struct Worker {
             if (words <= A.gcache_words) {
                 for (uint32_t i = lane(); i < words; i += 64) G[i] = ld_coh(&src[i]);
                 wave_sync();
-                voff = G;
+                vlds = true;
+                GC = G + n + 1u;
             } else {
                 // an instance graph of a batch too large for the cache: read
                 // in place (written before the search started)
-                voff = src;
+                vlds = false;
+                goff = src;
+                gcol = src + n + 1u;
             }
-            vcol = voff + n + 1;
             vn = n;
         }
         vpad = (vn + 63u) & ~63u;
         vbw = vpad / 32u;
         view = v;
     }
+
+    __device__ __forceinline__ uint32_t vo(uint32_t v) const { return vlds ? G[v] : goff[v]; }
+    __device__ __forceinline__ uint32_t vc(uint32_t e) const { return vlds ? GC[e] : gcol[e]; }
 
     // vertex count of view vw
     __device__ __forceinline__ uint32_t view_n(int vw) {
@@ -205,50 +267,35 @@ struct Worker {
 
     // ------------------------------------------------------- live list
 
+    // L = the live vertices of the view, in id order
     __device__ __forceinline__ void build_live() {
         const uint32_t l = lane();
         uint32_t cnt = 0;
-        uint64_t sum = 0, k = 0;
         for (uint32_t base = 0; base < vn; base += 64) {
-            uint32_t v = base + l;
-            uint32_t d = v < vn ? DG::get(deg, v) : 0u;
-            bool lv = DG::live(d);
-            uint64_t m = ballot(lv);
-            if (lv) {
-                L[cnt + mbcnt(m)] = v;
-                sum += d;
-                uint64_t kk = ((uint64_t)d << 32) | (uint32_t)~v;
-                k = kk > k ? kk : k;
-            }
+            const uint32_t v = base + l;
+            const bool lv = v < vn && DG::live(DG::get(deg, v));
+            const uint64_t m = ballot(lv);
+            if (lv) L[cnt + mbcnt(m)] = v;
             cnt += popc(m);
         }
         nl = cnt;
-        e2 = wave_sum64(sum);
-        key = wave_max64(k);
         wave_sync();
     }
 
+    // drop the vertices of L that are no longer live (order kept)
     __device__ __forceinline__ void recompact() {
         const uint32_t l = lane();
         uint32_t cnt = 0;
-        uint64_t sum = 0, k = 0;
         for (uint32_t base = 0; base < nl; base += 64) {
-            uint32_t i = base + l;
-            uint32_t v = i < nl ? L[i] : 0u;
-            uint32_t d = i < nl ? DG::get(deg, v) : 0u;
-            bool lv = DG::live(d);
-            uint64_t m = ballot(lv);
-            if (lv) {
-                L[cnt + mbcnt(m)] = v;
-                sum += d;
-                uint64_t kk = ((uint64_t)d << 32) | (uint32_t)~v;
-                k = kk > k ? kk : k;
-            }
+            const uint32_t i = base + l;
+            const uint32_t v = i < nl ? L[i] : 0u;
+            const bool lv = i < nl && DG::live(DG::get(deg, v));
+            const uint64_t m = ballot(lv);
+            wave_sync();  // every lane has read its entry before any moves
+            if (lv) L[cnt + mbcnt(m)] = v;
             cnt += popc(m);
         }
         nl = cnt;
-        e2 = wave_sum64(sum);
-        key = wave_max64(k);
         wave_sync();
     }
 
@@ -266,7 +313,8 @@ struct Worker {
             nn += popc(m);
         }
         wave_sync();
-        for_rows(voff, vcol, list, nn, [&](bool ok, uint32_t, uint32_t w) {
+        for_rows([&](uint32_t x) { return vo(x); }, [&](uint32_t e) { return vc(e); }, list, nn, MK,
+                 [&](bool ok, uint32_t, uint32_t w) {
             if (ok && DG::live(DG::get(deg, w))) DG::dec(deg, w);
         });
         wave_sync();
@@ -276,15 +324,51 @@ struct Worker {
 
     // ------------------------------------------------------- reduce
 
+    // is w in row u (the shorter of the two rows is scanned, four entries
+    // per LDS round trip)
     __device__ __forceinline__ bool adjacent(uint32_t u, uint32_t w) {
         uint32_t a = u, b = w;
-        if (voff[w + 1] - voff[w] < voff[u + 1] - voff[u]) {
+        if (vo(w + 1) - vo(w) < vo(u + 1) - vo(u)) {
             a = w;
             b = u;
         }
-        for (uint32_t e = voff[a]; e < voff[a + 1]; ++e)
-            if (vcol[e] == b) return true;
+        const uint32_t end = vo(a + 1);
+        for (uint32_t e = vo(a); e < end; e += 4) {
+            uint32_t x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = e + k < end ? vc(e + k) : NONE;
+            if (x[0] == b || x[1] == b || x[2] == b || x[3] == b) return true;
+        }
         return false;
+    }
+
+    // the first d (1 or 2) live neighbours of v in row order; returns how
+    // many were found
+    __device__ __forceinline__ uint32_t live_nbrs(uint32_t v, uint32_t d, uint32_t& u,
+                                                  uint32_t& w) {
+        const uint32_t end = vo(v + 1);
+        uint32_t got = 0;
+        u = w = NONE;
+        for (uint32_t e = vo(v); got < d && e < end; e += 4) {
+            uint32_t x[4];
+            bool ok[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ok[k] = e + k < end;
+                x[k] = ok[k] ? vc(e + k) : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ok[k] = ok[k] && DG::live(DG::get(deg, x[k]));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (ok[k] && got < d) {
+                    if (got == 0) u = x[k];
+                    else w = x[k];
+                    ++got;
+                }
+            }
+        }
+        return got;
     }
 
     // Reduction rules of Sec. II-B to a joint fixpoint.  Applied in parallel
@@ -293,49 +377,63 @@ struct Worker {
     // degree-two-triangle rules at once, where a degree-one vertex whose
     // neighbour also has degree one defers to the lower id, and of the
     // degree-two vertices of one triangle only the lowest id fires, so the
-    // joint effect equals some sequential order.  Returns false if pruned.
+    // joint effect equals some sequential order.  One sweep over the live
+    // list finds the high-degree vertices and, into Q, the vertices of
+    // degree one or two; the rules of (2) then run on that compacted list,
+    // so every lane of a chunk has a row to walk.  Returns false if pruned.
     __device__ __forceinline__ bool reduce() {
         const uint32_t l = lane();
         bool changed_any = false;
         for (;;) {
             if (s >= best) return false;
             const int64_t b = (int64_t)best - s - 1;
-            // (1) high degree
-            uint32_t cnt = 0;
+            uint32_t hc = 0, cc = 0;
+            uint32_t dsum = 0;  // per lane: at most n/64 degrees of at most n
+            uint64_t k = 0;     // max of (degree << 32 | ~id)
+            uint32_t vn_next = nl ? L[l < nl ? l : 0] : 0u;
             for (uint32_t base = 0; base < nl; base += 64) {
-                uint32_t i = base + l;
-                uint32_t v = i < nl ? L[i] : 0u;
-                bool f = i < nl && (int64_t)DG::get(deg, v) > b;
-                uint64_t m = ballot(f);
-                if (f) R[cnt + mbcnt(m)] = v;
-                cnt += popc(m);
+                const uint32_t i = base + l;
+                const uint32_t v = vn_next;
+                if (base + 64u < nl) vn_next = L[i + 64u < nl ? i + 64u : base + 64u];
+                const uint32_t d = i < nl ? DG::get(deg, v) : 0u;
+                const bool hi = i < nl && (int64_t)d > b;
+                const bool c12 = i < nl && (d == 1u || d == 2u);
+                const uint64_t mh = ballot(hi);
+                const uint64_t mc = ballot(c12);
+                if (hi) R[hc + mbcnt(mh)] = v;
+                if (c12) Q[cc + mbcnt(mc)] = v;
+                hc += popc(mh);
+                cc += popc(mc);
+                if (i < nl) {
+                    dsum += d;
+                    const uint64_t kk = ((uint64_t)d << 32) | (uint32_t)~v;
+                    k = kk > k ? kk : k;
+                }
             }
             wave_sync();
-            if (cnt) {
-                take_list(R, cnt);
+            // 2|E| and the branching key of the current live set (final
+            // once a round applies no rule)
+            e2 = wave_sum(dsum);
+            key = wave_max64(k);
+            // (1) high degree first
+            if (hc) {
+                take_list(R, hc);
                 recompact();
                 changed_any = true;
                 continue;
             }
-            // (2) degree one / degree-two triangle
-            for (uint32_t base = 0; base < nl; base += 64) {
-                uint32_t i = base + l;
-                uint32_t v = i < nl ? L[i] : 0u;
-                uint32_t d = i < nl ? DG::get(deg, v) : 0u;
+            // (2) degree one / degree-two triangle, over the candidates
+            uint32_t cnt = 0;
+            for (uint32_t base = 0; base < cc; base += 64) {
+                const uint32_t i = base + l;
+                const uint32_t v = i < cc ? Q[i] : 0u;
+                const uint32_t d = i < cc ? DG::get(deg, v) : 0u;
                 uint32_t u = NONE, w = NONE;
                 bool add_u = false, add_w = false;
-                if (d == 1u || d == 2u) {
-                    uint32_t got = 0;
-                    for (uint32_t e = voff[v]; e < voff[v + 1] && got < d; ++e) {
-                        uint32_t x = vcol[e];
-                        if (DG::live(DG::get(deg, x))) {
-                            if (got == 0) u = x; else w = x;
-                            ++got;
-                        }
-                    }
-                    if (got < d) {
-                        // inconsistent input (not a simple symmetric graph): no rule
-                    } else if (d == 1u) {
+                if (i < cc && live_nbrs(v, d, u, w) == d) {
+                    // (fewer than d live neighbours would mean an inconsistent
+                    // input, not a simple symmetric graph: no rule then)
+                    if (d == 1u) {
                         add_u = !(DG::get(deg, u) == 1u && u < v);
                     } else if (adjacent(u, w)) {
                         add_u = !(DG::get(deg, u) == 2u && u < v) &&
@@ -343,10 +441,10 @@ struct Worker {
                         add_w = add_u;
                     }
                 }
-                uint64_t m1 = ballot(add_u);
+                const uint64_t m1 = ballot(add_u);
                 if (add_u) R[cnt + mbcnt(m1)] = u;
                 cnt += popc(m1);
-                uint64_t m2 = ballot(add_w);
+                const uint64_t m2 = ballot(add_w);
                 if (add_w) R[cnt + mbcnt(m2)] = w;
                 cnt += popc(m2);
             }
@@ -402,7 +500,8 @@ struct Worker {
             uint32_t fa = qn - 1, fb = qn, level = 0;
             while (fa < fb) {
                 const bool odd = ((level + 1u) & 1u) != 0u;
-                for_rows(voff, vcol, Q + fa, fb - fa, [&](bool ok, uint32_t, uint32_t w) {
+                for_rows([&](uint32_t x) { return vo(x); }, [&](uint32_t e) { return vc(e); },
+                         Q + fa, fb - fa, MK, [&](bool ok, uint32_t, uint32_t w) {
                     bool nw = false;
                     if (ok && DG::live(DG::get(deg, w))) {
                         uint32_t bit = 1u << (w & 31u);
@@ -520,10 +619,10 @@ struct Worker {
     __device__ __forceinline__ void take_neighbours(uint32_t v) {
         const uint32_t l = lane();
         uint32_t cnt = 0;
-        const uint32_t r0 = voff[v], r1 = voff[v + 1];
+        const uint32_t r0 = vo(v), r1 = vo(v + 1);
         for (uint32_t e0 = r0; e0 < r1; e0 += 64) {
             uint32_t e = e0 + l;
-            uint32_t w = e < r1 ? vcol[e] : 0u;
+            uint32_t w = e < r1 ? vc(e) : 0u;
             bool lv = e < r1 && DG::live(DG::get(deg, w));
             uint64_t m = ballot(lv);
             if (lv) R[cnt + mbcnt(m)] = w;
@@ -541,19 +640,10 @@ struct Worker {
         order_point();
     }
 
-    __device__ __forceinline__ bool hungry(uint32_t live) {
+    // idle workers outnumber queued nodes (by the last poll)
+    __device__ __forceinline__ bool others_hungry() {
         if (A.flags & VC_OPT_NO_LOAD_BALANCE) return false;
-        if (live < A.donate_min) return false;
-        int idle = 0;
-        uint64_t h = 0, t = 0;
-        if (lane() == 0) {
-            idle = ld_relaxed(&A.ctl->idle);
-            h = ld_relaxed(&A.ctl->wl_head);
-            t = ld_relaxed(&A.ctl->wl_tail);
-        }
-        idle = uni(idle);
-        uint64_t q = uni(t) - uni(h);
-        return idle > 0 && (uint64_t)idle > q + A.donate_slack;
+        return c_idle > 0 && (int64_t)c_idle > c_queued + (int64_t)A.donate_slack;
     }
 
     // reserve a worklist position (UINT64_MAX when full)
@@ -582,6 +672,7 @@ struct Worker {
     }
 
     __device__ __forceinline__ void wl_publish(uint64_t pos) {
+        ++c_queued;  // until the next poll
         wave_sync();
         if (lane() == 0) {
             add_relaxed(&A.ctl->outstanding, 1);
@@ -654,13 +745,18 @@ struct Worker {
         ++pushes;
         // the threshold applies to what would be donated: the oldest
         // pending node when there is one, else this one
-        uint32_t cand = live;
-        if (top > bot) {
-            uint32_t nlv = 0;
-            if (lane() == 0) nlv = reinterpret_cast<const SlotHdr*>(stack + (size_t)bot * A.slot_bytes)->nlive;
-            cand = uni(nlv);
+        bool give = false;
+        if (others_hungry()) {
+            uint32_t cand = live;
+            if (top > bot) {
+                uint32_t nlv = 0;
+                if (lane() == 0)
+                    nlv = reinterpret_cast<const SlotHdr*>(stack + (size_t)bot * A.slot_bytes)->nlive;
+                cand = uni(nlv);
+            }
+            give = cand >= A.donate_min;
         }
-        if (hungry(cand)) {
+        if (give) {
             // give away the oldest pending node (it roots the largest subtree)
             // when there is one, else this one
             uint64_t pos = wl_reserve();
@@ -804,6 +900,7 @@ struct Worker {
         int old = 0;
         if (lane() == 0) old = min_relaxed(&A.reg[e].best, val);
         old = uni(old);
+        if (e == c_best_scope) c_best = old < val ? old : val;
         if (val >= old) return false;
         lock(e);
         const int cs = reg_field(&A.reg[e].cover_size);
@@ -935,6 +1032,7 @@ struct Worker {
         if (i == inst) return;
         flush_inst();
         inst = i;
+        since_poll = POLL_EVERY;  // the cached instance state is another's
     }
 
     __device__ __forceinline__ void count_node() {
@@ -953,15 +1051,9 @@ struct Worker {
     // answer or is over its limit, so the node is dropped
     enum { GO = 0, STOP_ALL = 1, DROP = 2 };
     __device__ __forceinline__ int stop_requested(bool force) {
-        if (!force && ++since_check < 8) return GO;
-        since_check = 0;
-        int d = 0, is = 0;
-        if (lane() == 0) {
-            d = ld_relaxed(&A.ctl->done);
-            if (A.batch) is = ld_relaxed(&A.inst_state[inst]);
-        }
-        if (uni(d) != 0) return STOP_ALL;
-        return (uni(is) & INST_STOP) ? DROP : GO;
+        if (force || ++since_poll >= POLL_EVERY) poll();
+        if (c_done != 0) return STOP_ALL;
+        return (c_inst_state & INST_STOP) ? DROP : GO;
     }
 
     // vertex branch on v_max: the G - N(v) child is pushed (lazily, as the
@@ -1072,8 +1164,9 @@ struct Worker {
         for (uint32_t i = l; i < size; i += 64) {
             const uint32_t v = Q[a + i];
             uint32_t pos = CUR[i];
-            for (uint32_t e = voff[v]; e < voff[v + 1]; ++e) {
-                const uint32_t w = vcol[e];
+            const uint32_t r1 = vo(v + 1);
+            for (uint32_t e = vo(v); e < r1; ++e) {
+                const uint32_t w = vc(e);
                 if (DG::live(DG::get(deg, w))) st_coh(&gc[pos++], M[w]);
             }
         }
@@ -1094,6 +1187,7 @@ struct Worker {
         // the bound may have improved since the node started: every
         // component needs at least one vertex
         const int bnow = scope_best(scope);
+        if (scope == c_best_scope) c_best = bnow;
         const int base_sum = s;
         if ((int64_t)base_sum + nt >= (int64_t)bnow) return CB_PRUNED;
         const uint32_t want = (nt + 1u + 1u) & ~1u;  // whole 128-byte lines
@@ -1247,7 +1341,7 @@ struct Worker {
                 charge(CYC_COMPLETE);
                 return false;
             }
-            best = scope_best(scope);
+            best = cur_best();
             const bool alive = reduce();
             charge(CYC_REDUCE);
             if (!alive) {
@@ -1299,6 +1393,14 @@ struct Worker {
                         charge(CYC_COMPLETE);
                         return false;
                     }
+                    // registry full: branch on a vertex instead; if simple
+                    // components were just settled, the rules (and the
+                    // branching key) first run again on what is left
+                    if (nt != nc) {
+                        known_connected = true;
+                        recount = false;
+                        continue;
+                    }
                 }
             }
             const bool ok = vertex_branch();
@@ -1345,7 +1447,7 @@ struct Worker {
         set_inst(got);
         load_view((int)got);
         for (uint32_t v = lane(); v < vpad; v += 64)
-            DG::set(deg, v, v < vn ? voff[v + 1] - voff[v] : 0u);
+            DG::set(deg, v, v < vn ? vo(v + 1) - vo(v) : 0u);
         wave_sync();
         s = 0;
         scope = (int)got;
@@ -1361,9 +1463,13 @@ struct Worker {
                 begin_node(copy_slot(stack + (size_t)top * A.slot_bytes));
                 if (top == bot) bot = top = 0;
                 charge(CYC_FETCH);
+                if (process(false)) break;
+                continue;
             } else {
                 bot = top = 0;
                 if (busy && lane() == 0) add_relaxed(&A.ctl->outstanding, -1);
+                // (a node from the worklist or a new instance starts with a
+                // fresh poll; nodes from the own stack use the cached state)
                 busy = false;
                 if (claim_instance()) {
                     busy = true;
