@@ -92,6 +92,13 @@ typedef struct {
  *                 subtree is too small to pay for the move).  A donating
  *                 worker gives away its oldest pending node, so the test
  *                 applies to that node (default 48).
+ *   serve_n_max   serving: the largest induced subgraph (vertices after the
+ *                 root reduction) a request may leave for the resident
+ *                 search (default 4096); larger ones run alone between
+ *                 resident launches.
+ *   serve_slots   serving: instance slots of one resident launch (default
+ *                 4096); when they or its graph arena run out, the resident
+ *                 kernel drains and is launched again.
  *   gcache_words  LDS graph cache per worker, in 32-bit words: components
  *                 whose induced subgraph fits are re-induced with local ids
  *                 (default: the most that still fits three workers per CU).
@@ -107,6 +114,8 @@ typedef struct {
     uint32_t watchdog_ms;
     uint32_t donate_min;
     uint32_t gcache_words;
+    uint32_t serve_n_max;
+    uint32_t serve_slots;
 } vc_opts;
 
 /* Statistics of the last completed solve on a context. */
@@ -234,6 +243,52 @@ vc_status vc_min_batch(vc_ctx *ctx, const vc_batch *b, uint32_t *sizes,
 vc_status vc_param_batch(vc_ctx *ctx, const vc_batch *b, const uint32_t *k,
                          int *yes, int32_t *inst_status, uint32_t *covers,
                          uint64_t *cover_offs);
+
+/* vc_submit kinds */
+#define VC_MIN 0   /* minimum vertex cover                                 */
+#define VC_PARAM 1 /* parameterized: is there a cover of size <= k         */
+
+/* The outcome of a served request (vc_poll). */
+typedef struct {
+    int32_t status;        /* VC_OK, or the request's error status          */
+    int32_t kind;          /* VC_MIN or VC_PARAM                            */
+    uint32_t size;         /* VC_MIN: MVC; VC_PARAM yes: size of the cover  */
+    int32_t yes;           /* VC_PARAM: 1 iff MVC <= k                      */
+    uint32_t cover_len;    /* vertices written to the cover array           */
+    uint32_t n;            /* vertices of the request's graph               */
+    uint64_t tree_nodes;   /* search-tree nodes spent on the request        */
+    double ms_queued;      /* submit -> admitted to the resident search     */
+    double ms_latency;     /* submit -> result ready                        */
+} vc_result;
+
+/*
+ * Serving (continuous batching).  vc_submit copies the graph (host or
+ * device CSR) and returns at once with a ticket; a server thread of the
+ * context runs the request's root reduction and induce steps on a side
+ * stream and then admits its induced subgraph, by HBM footprint (an
+ * instance slot and room in the graph arena), into a resident persistent
+ * search kernel that is already working on the other admitted requests:
+ * idle workers pick the new instance up while the others run (each request
+ * is an instance as in vc_min_batch).  Requests whose root steps already
+ * decide them never reach the search.  Thread-safe: vc_submit, vc_poll and
+ * vc_cancel may be called from any thread.  While requests are in flight no
+ * other solve may run on the context (VC_EAGAIN).
+ *   kind  VC_MIN or VC_PARAM (then k is the bound).
+ */
+vc_status vc_submit(vc_ctx *ctx, const vc_csr *g, int kind, uint32_t k,
+                    uint64_t *ticket);
+
+/*
+ * VC_EAGAIN while the request is pending; otherwise fills *out and, if
+ * cover is not NULL, the cover (ascending ids, capacity n), returns VC_OK
+ * and forgets the ticket.  A cancelled request returns VC_ECANCELED (also
+ * forgotten); an unknown ticket VC_EINVAL.
+ */
+vc_status vc_poll(vc_ctx *ctx, uint64_t ticket, vc_result *out,
+                  uint32_t *cover);
+
+/* Cancel a pending request: it is dropped before or during its search. */
+vc_status vc_cancel(vc_ctx *ctx, uint64_t ticket);
 
 /* Copy the statistics of the last completed solve. */
 vc_status vc_last_stats(vc_ctx *ctx, vc_stats *out);

@@ -457,6 +457,22 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
 
 }  // namespace
 
+namespace vc {
+
+vc_status solve_one(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, uint32_t* size, int* yes,
+                    uint32_t* cover, uint32_t* cover_len) {
+    if (pvc && k > 0x3FFFFFF0u) k = 0x3FFFFFF0u;
+    Outcome o;
+    vc_status st = solve(c, g, pvc, k, &o, cover, cover_len);
+    if (st) return st;
+    if (size) *size = o.size;
+    if (yes) *yes = o.yes;
+    if (pvc && !o.yes && cover_len) *cover_len = 0;
+    return VC_OK;
+}
+
+}  // namespace vc
+
 extern "C" {
 
 vc_status vc_ctx_create(int device, void* stream, const vc_opts* opts, vc_ctx** out) {
@@ -522,6 +538,7 @@ vc_status vc_ctx_create(int device, void* stream, const vc_opts* opts, vc_ctx** 
 vc_status vc_ctx_destroy(vc_ctx* c) {
     if (!c) return VC_OK;
     hipSetDevice(c->device);
+    server_shutdown(c);
     if (c->stream) hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->in_off, &c->in_col, &c->rdeg, &c->gdeg, &c->gin, &c->addf,
                       &c->newly, &c->flags, &c->newid, &c->oldid, &c->kdeg, &c->koff,
@@ -554,25 +571,17 @@ vc_status vc_validate(vc_ctx* c, const vc_csr* g) {
 vc_status vc_min(vc_ctx* c, const vc_csr* g, uint32_t* size, uint32_t* cover,
                  uint32_t* cover_len) {
     if (!c || !size) return VC_EINVAL;
+    if (server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
-    Outcome o;
-    vc_status st = solve(c, g, 0, 0, &o, cover, cover_len);
-    if (st) return st;
-    *size = o.size;
-    return VC_OK;
+    return solve_one(c, g, 0, 0, size, nullptr, cover, cover_len);
 }
 
 vc_status vc_param(vc_ctx* c, const vc_csr* g, uint32_t k, int* yes, uint32_t* cover,
                    uint32_t* cover_len) {
     if (!c || !yes) return VC_EINVAL;
-    if (k > 0x3FFFFFF0u) k = 0x3FFFFFF0u;
+    if (server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
-    Outcome o;
-    vc_status st = solve(c, g, 1, k, &o, cover, cover_len);
-    if (st) return st;
-    *yes = o.yes;
-    if (!o.yes && cover_len) *cover_len = 0;
-    return VC_OK;
+    return solve_one(c, g, 1, k, nullptr, yes, cover, cover_len);
 }
 
 vc_status vc_last_stats(vc_ctx* c, vc_stats* out) {

@@ -459,6 +459,7 @@ vc_status vc_min_batch(vc_ctx* c, const vc_batch* b, uint32_t* sizes, int32_t* i
                        uint32_t* covers, uint64_t* cover_offs) {
     if (!c || !b || !sizes) return VC_EINVAL;
     if ((covers == nullptr) != (cover_offs == nullptr)) return VC_EINVAL;
+    if (server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
     BatchOut o;
     vc_status st = run_batch(c, b, 0, nullptr, &o);
@@ -488,6 +489,7 @@ vc_status vc_param_batch(vc_ctx* c, const vc_batch* b, const uint32_t* k, int* y
                          int32_t* inst_status, uint32_t* covers, uint64_t* cover_offs) {
     if (!c || !b || !k || !yes) return VC_EINVAL;
     if ((covers == nullptr) != (cover_offs == nullptr)) return VC_EINVAL;
+    if (server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
     BatchOut o;
     vc_status st = run_batch(c, b, 1, k, &o);

@@ -58,6 +58,10 @@ inline vc_status hip_status(hipError_t e) {
         }                                                                         \
     } while (0)
 
+namespace vc {
+struct Server;
+}
+
 struct vc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -79,6 +83,8 @@ struct vc_ctx {
     // the captured batch launch and the arguments it was captured with
     hipGraphExec_t batch_exec = nullptr;
     std::vector<unsigned char> batch_key;
+    // serving (vc_submit): created on the first request
+    vc::Server* srv = nullptr;
     hipEvent_t ev[6] = {};
 };
 
@@ -88,4 +94,12 @@ vc_status validate_host(const vc_csr* g);
 vc_status check_args(const vc_csr* g);
 vc_status plan_workers(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* lp,
                        uint32_t* gwords, uint32_t* workers);
+// one blocking solve on the context's own buffers and stream (vc_min and
+// vc_param; also the server for requests too large for its resident search)
+vc_status solve_one(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, uint32_t* size, int* yes,
+                    uint32_t* cover, uint32_t* cover_len);
+// serving: true while requests are in flight (other solves must wait)
+bool server_busy(vc_ctx* c);
+// stop the server thread and its resident kernel (context teardown)
+void server_shutdown(vc_ctx* c);
 }  // namespace vc

@@ -76,6 +76,9 @@ struct Ctl {
     uint64_t _p6[15];
     uint32_t inst_next;   // batches: next instance to claim
     uint32_t _p8[31];
+    uint32_t inst_avail;  // serving: instances published so far (host writes)
+    int closed;           // serving: no more instances will be published
+    uint32_t _p9[30];
     uint64_t nodes;   // statistics
     uint64_t comp_branches;
     uint64_t components;
@@ -139,6 +142,12 @@ struct SearchArgs {
     uint64_t* inst_nodes;     // [n_roots] tree nodes per instance
     const int* inst_k;        // [n_roots] PVC bound per instance (batch PVC)
     uint64_t inst_node_limit; // per instance, 0: none
+    // Serving: instances 0 .. Ctl::inst_avail-1 are published while the
+    // kernel runs (n_roots is the slot capacity); the kernel ends once
+    // Ctl::closed is set and no work is left.  inst_cancel[i] != 0 stops
+    // instance i like a PVC answer does.
+    uint32_t serve;
+    const int* inst_cancel;
 };
 
 // LDS layout of one worker: degree array, live list L, scratch lists Q and
@@ -187,6 +196,9 @@ struct BatchDesc {
     uint64_t inst_words;        // arena words taken by the instance graphs
 };
 hipError_t launch_batch_pack(const SearchArgs& a, const BatchDesc& d, hipStream_t st);
+// serving: the control block and worklist of a resident launch; the graph
+// arena's first host_words words hold the instances' graphs
+hipError_t launch_serve_init(const SearchArgs& a, uint64_t host_words, hipStream_t st);
 hipError_t launch_batch_init(const SearchArgs& a, const BatchDesc& d, hipStream_t st);
 // cover lists: instance i's root bitmap as ascending ids at out + cbase[i],
 // the count in cnt[i]

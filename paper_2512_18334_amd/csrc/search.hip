@@ -177,6 +177,7 @@ struct Worker {
         if (lane() == 0) {
             d = ld_relaxed(&A.ctl->done);
             if (A.batch) is = ld_relaxed(&A.inst_state[inst]);
+            if (A.serve && ld_relaxed(&A.inst_cancel[inst])) is |= INST_STOP;
             idl = ld_relaxed(&A.ctl->idle);
             h = ld_relaxed(&A.ctl->wl_head);
             t = ld_relaxed(&A.ctl->wl_tail);
@@ -257,8 +258,14 @@ struct Worker {
         view = v;
     }
 
-    __device__ __forceinline__ uint32_t vo(uint32_t v) const { return vlds ? G[v] : goff[v]; }
-    __device__ __forceinline__ uint32_t vc(uint32_t e) const { return vlds ? GC[e] : gcol[e]; }
+    // (a served instance's graph is written while the kernel runs, so it is
+    // read with coherent loads)
+    __device__ __forceinline__ uint32_t vo(uint32_t v) const {
+        return vlds ? G[v] : (A.serve ? ld_coh(&goff[v]) : goff[v]);
+    }
+    __device__ __forceinline__ uint32_t vc(uint32_t e) const {
+        return vlds ? GC[e] : (A.serve ? ld_coh(&gcol[e]) : gcol[e]);
+    }
 
     // vertex count of view vw
     __device__ __forceinline__ uint32_t view_n(int vw) {
@@ -858,7 +865,7 @@ struct Worker {
         const bool wrote = improve_once(e, val, from, &prev_cs);
         // PVC (Sec. III-E): a component's better cover travels up the
         // registry chain at once, so the root learns when it is within k
-        if (wrote && A.pvc && !is_root(e)) propagate_up(e, prev_cs, val);
+        if (wrote && pvc_now() && !is_root(e)) propagate_up(e, prev_cs, val);
         return wrote;
     }
 
@@ -897,6 +904,7 @@ struct Worker {
     }
 
     __device__ __forceinline__ bool improve_once(int e, int val, int from, int* prev_cs) {
+        const bool pvc = pvc_now();
         int old = 0;
         if (lane() == 0) old = min_relaxed(&A.reg[e].best, val);
         old = uni(old);
@@ -920,7 +928,7 @@ struct Worker {
                     // in PVC the children may still be improving: read each
                     // child's cover under its lock (ancestor locks are always
                     // taken before descendant locks)
-                    if (A.pvc) lock(c);
+                    if (pvc) lock(c);
                     const int cv = reg_field(&A.reg[c].view);
                     if (cv == c) {
                         const uint32_t cn = (uint32_t)reg_field(&A.reg[c].vn);
@@ -942,7 +950,7 @@ struct Worker {
                         }
                     }
                     wave_sync();
-                    if (A.pvc) unlock(c);
+                    if (pvc) unlock(c);
                 }
                 for (uint32_t wi = l; wi < ebw; wi += 64) st_coh(&dst[wi], VB[wi]);
             }
@@ -952,7 +960,7 @@ struct Worker {
             wrote = true;
         }
         unlock(e);
-        if (A.pvc && is_root(e) && val <= (A.batch ? A.inst_k[e] : A.k) && lane() == 0) {
+        if (is_root(e) && pvc_now() && val <= (A.batch ? A.inst_k[e] : A.k) && lane() == 0) {
             if (A.batch)
                 __hip_atomic_fetch_or(&A.inst_state[e], INST_STOP, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
@@ -966,6 +974,15 @@ struct Worker {
     // descendant of a component adds its Best to the parent's Sum; the last
     // component of a parent offers Sum to the ancestor's Best and finishes
     // the parent node in the ancestor's scope (Sec. III-C).
+    // PVC semantics for the current node: the solve's, or when serving the
+    // instance's (a served MVC request has no bound k: inst_k < 0)
+    __device__ __forceinline__ bool pvc_now() {
+        if (!A.serve) return A.pvc != 0;
+        int kk = -1;
+        if (lane() == 0) kk = ld_relaxed(&A.inst_k[inst]);
+        return uni(kk) >= 0;
+    }
+
     // Live-node counts are kept for every scope except the root of a single
     // solve (its end is the end of the search).
     __device__ __forceinline__ bool counted(int e) { return A.batch || e != 0; }
@@ -1428,19 +1445,30 @@ struct Worker {
     __device__ __forceinline__ bool claim_instance() {
         if (!A.batch) return false;
         uint32_t got = NONE;
-        if (lane() == 0 && ld_relaxed(&A.ctl->inst_next) < A.n_roots) {
-            // count this worker as busy first, so that no idle worker sees
-            // zero outstanding work while an instance is being claimed
-            add_relaxed(&A.ctl->outstanding, 1);
-            for (;;) {
-                const uint32_t i = atomicAdd(&A.ctl->inst_next, 1u);
-                if (i >= A.n_roots) break;
-                // instances answered during set-up have no root node
-                if (ld_relaxed(&A.inst_state[i]) & INST_FIN) continue;
-                got = i;
-                break;
+        if (lane() == 0) {
+            // instances 0 .. limit-1 exist: all of a batch, the published
+            // ones when serving
+            const uint32_t limit = A.serve ? ld_relaxed(&A.ctl->inst_avail) : A.n_roots;
+            if (ld_relaxed(&A.ctl->inst_next) < limit) {
+                // count this worker as busy first, so that no idle worker
+                // sees zero outstanding work while an instance is claimed
+                add_relaxed(&A.ctl->outstanding, 1);
+                uint32_t cur = ld_relaxed(&A.ctl->inst_next);
+                while (cur < limit) {
+                    const uint32_t prev = atomicCAS(&A.ctl->inst_next, cur, cur + 1u);
+                    if (prev != cur) {
+                        cur = prev;
+                        continue;
+                    }
+                    // instances answered during set-up have no root node
+                    if (!(ld_relaxed(&A.inst_state[cur]) & INST_FIN)) {
+                        got = cur;
+                        break;
+                    }
+                    cur = ld_relaxed(&A.ctl->inst_next);
+                }
+                if (got == NONE) add_relaxed(&A.ctl->outstanding, -1);
             }
-            if (got == NONE) add_relaxed(&A.ctl->outstanding, -1);
         }
         got = uni(got);
         if (got == NONE) return false;
@@ -1479,8 +1507,8 @@ struct Worker {
                 }
                 if (lane() == 0) add_relaxed(&A.ctl->idle, 1);
                 uint32_t spins = 0;
-                bool got = false, quit = false;
-                const uint64_t t_idle = wall_clock64();
+                bool got = false, quit = false, claimed = false;
+                uint64_t t_idle = wall_clock64();
                 // poll the queue tail only; head, the outstanding count and
                 // the stop flag are read when it moved or every 16th round
                 uint64_t seen_tail = ~0ull;
@@ -1490,16 +1518,25 @@ struct Worker {
                     t = uni(t);
                     if (t != seen_tail || (round & 15u) == 0) {
                         seen_tail = t;
-                        int d = 0, outst = 0;
+                        int d = 0, outst = 0, closed = 0;
                         uint64_t h = 0;
+                        uint32_t avail = 0, next = 0;
                         if (lane() == 0) {
                             d = ld_relaxed(&A.ctl->done);
                             h = ld_relaxed(&A.ctl->wl_head);
                             outst = ld_relaxed(&A.ctl->outstanding);
+                            if (A.serve) {
+                                closed = ld_relaxed(&A.ctl->closed);
+                                avail = ld_relaxed(&A.ctl->inst_avail);
+                                next = ld_relaxed(&A.ctl->inst_next);
+                            }
                         }
                         d = uni(d);
                         outst = uni(outst);
                         h = uni(h);
+                        closed = uni(closed);
+                        avail = uni(avail);
+                        next = uni(next);
                         if (d) {
                             quit = true;
                             break;
@@ -1510,10 +1547,23 @@ struct Worker {
                                 break;
                             }
                             spins = 0;
-                        } else if (outst == 0) {
+                        } else if (next < avail) {
+                            // a request was published: take it as a new
+                            // instance (the claim counts this worker busy)
+                            if (lane() == 0) add_relaxed(&A.ctl->idle, -1);
+                            if (claim_instance()) {
+                                claimed = true;
+                                break;
+                            }
+                            if (lane() == 0) add_relaxed(&A.ctl->idle, 1);
+                            spins = 0;
+                        } else if (outst == 0 && (!A.serve || closed)) {
                             quit = true;
                             break;
                         }
+                        // waiting for requests while nothing is outstanding
+                        // is a served kernel's normal state
+                        if (A.serve && outst == 0) t_idle = wall_clock64();
                     }
                     if (wall_clock64() - t_idle > A.watchdog_ticks) {
                         // waited far longer than any node takes: give up
@@ -1523,10 +1573,10 @@ struct Worker {
                     }
                     if (lane() == 0) backoff(spins);
                 }
-                if (lane() == 0) add_relaxed(&A.ctl->idle, -1);
+                if (!claimed && lane() == 0) add_relaxed(&A.ctl->idle, -1);
                 charge(CYC_IDLE);
                 if (quit) break;
-                busy = got;
+                busy = got || claimed;
             }
             if (process(true)) break;
         }
@@ -1775,6 +1825,40 @@ hipError_t launch_batch_cover(const SearchArgs& a, const BatchDesc& d, const uin
                               uint32_t* out, uint32_t* cnt, hipStream_t st) {
     const uint32_t blocks = d.count < 8192u ? (d.count ? d.count : 1u) : 8192u;
     hipLaunchKernelGGL(batch_cover_kernel, dim3(blocks), dim3(64), 0, st, a, d, cbase, out, cnt);
+    return hipGetLastError();
+}
+
+// Serving: the empty worklist and the control block of a resident launch
+// (instances are published into it later by the host).
+__global__ void serve_init_kernel(SearchArgs a, uint64_t host_words) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = tid; i < a.wl_cap; i += stride) a.wl_seq[i] = (uint64_t)i;
+    if (tid == 0) {
+        Ctl* c = a.ctl;
+        c->wl_head = 0;
+        c->wl_tail = 0;
+        c->outstanding = 0;
+        c->idle = 0;
+        c->done = 0;
+        c->err = 0;
+        c->reg_next = (a.n_roots + 1u) & ~1u;
+        c->arena_next = host_words;
+        c->inst_next = 0;
+        c->inst_avail = 0;
+        c->closed = 0;
+        c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
+        c->stale = c->local_views = 0;
+        for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
+        c->bytes_nodes = c->bytes_registry = 0;
+    }
+}
+
+hipError_t launch_serve_init(const SearchArgs& a, uint64_t host_words, hipStream_t st) {
+    uint32_t blocks = (a.wl_cap + 255u) / 256u;
+    if (blocks > 1024u) blocks = 1024u;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(serve_init_kernel, dim3(blocks), dim3(256), 0, st, a, host_words);
     return hipGetLastError();
 }
 

@@ -1,0 +1,806 @@
+// serve.hip -- serving with continuous batching (vc_submit, vc_poll,
+// vc_cancel).
+//
+// A server thread per context owns two streams: a side stream for the root
+// steps of each request (validation, greedy bound, root reduction, induce;
+// Sec. IV-B) and for publishing, and a search stream holding one resident
+// persistent search launch in serving mode.  A request whose root steps do
+// not decide it becomes an instance of that launch: its induced subgraph is
+// copied into the launch's graph arena, its root registry entry is written,
+// and the count of published instances is raised; an idle worker of the
+// running kernel then claims it (as in a batch) while the other instances
+// go on.  Admission is by footprint: an instance slot, arena room for the
+// induced subgraph and pool room for the maps that turn its result back
+// into original ids.  When a launch runs out of slots or room it drains and
+// is launched again; the server closes it as soon as nothing is left, so it
+// never sits on the GPU idle for long.  All device memory is allocated
+// while no resident launch runs (freeing memory may wait for the device).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ctx.hpp"
+#include "internal.hpp"
+#include "root.hpp"
+#include "vc.h"
+
+namespace vc {
+
+namespace {
+
+__global__ void k_srv_zero(uint32_t* p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+__global__ void k_srv_mark_list(const uint32_t* list, uint32_t cnt, uint32_t* flags) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x)
+        flags[list[i]] = 1u;
+}
+__global__ void k_srv_mark_bits(uint32_t np, const uint32_t* oldid, const uint32_t* bitmap,
+                                uint32_t* flags) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x)
+        if ((bitmap[i >> 5] >> (i & 31u)) & 1u) flags[oldid[i]] = 1u;
+}
+__global__ void k_srv_emit(uint32_t n, const uint32_t* flags, const uint32_t* pos, uint32_t* out) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (flags[v]) out[pos[v]] = v;
+}
+
+uint32_t grid_of(uint64_t n) {
+    uint64_t b = (n + 255) / 256;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b, 1), 4096);
+}
+
+struct Req {
+    uint64_t ticket = 0;
+    int kind = VC_MIN;
+    uint32_t k = 0;
+    uint32_t n = 0;
+    uint64_t nnz = 0;
+    uint32_t col_bytes = 4;
+    std::vector<uint32_t> off;
+    std::vector<uint8_t> col;
+    // root steps
+    uint32_t np = 0, sroot = 0, gsize = 0, dmax = 0, nforced = 0;
+    uint64_t nnzp = 0;
+    int kbest0 = 0;
+    uint64_t save_at = 0;  // pool words: forced list, greedy list, new -> old ids
+    uint32_t slot = 0;
+    bool admitted = false, cancel_sent = false;
+    // outcome
+    std::atomic<bool> canceled{false};
+    bool done = false;
+    vc_result res{};
+    std::vector<uint32_t> cover;
+    double t_submit = 0, t_admit = 0;
+};
+
+}  // namespace
+
+struct Server {
+    vc_ctx* c = nullptr;
+    // shared with the API threads (under mu)
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    uint64_t pending = 0;  // submitted and not finished
+    std::deque<std::shared_ptr<Req>> incoming;
+    std::unordered_map<uint64_t, std::shared_ptr<Req>> table;
+    std::thread th;
+    bool resident_flag = false;  // a resident launch exists (read by server_busy)
+
+    // owned by the server thread
+    hipStream_t ss = nullptr, ks = nullptr;
+    hipEvent_t ready = nullptr;
+    std::deque<std::shared_ptr<Req>> queue;
+    std::vector<std::shared_ptr<Req>> slot_req;
+    bool resident = false;
+    uint32_t published = 0, active = 0;
+    uint64_t host_next = 0, host_cap = 0, pool_next = 0, pool_cap = 0;
+    double idle_since = 0;
+    // root step buffers (capacity n_root vertices, nnz_root entries)
+    uint64_t n_root = 0, nnz_root = 0;
+    DevBuf in_off, in_col, rdeg, gdeg, gin, addf, newly, flags, newid, oldid, kdeg, koff, kcol,
+        cover, scan_tmp, ctr, hsum, pool;
+    // resident launch
+    DevBuf stacks, wl_slots, wl_seq, ctl, reg, bitmaps, arena, st, nodes, kk, cancel;
+    SearchArgs a{};
+    uint32_t deg_bytes = 2, workers = 0;
+    bool planned = false;
+    std::vector<int> h_state;
+    std::vector<uint64_t> h_nodes;
+
+    vc_status plan();
+    vc_status root_bufs(uint64_t n, uint64_t nnz, RootBufs* b);
+    vc_status open_resident();
+    vc_status close_resident();
+    vc_status start(Req& r);
+    vc_status finish(Req& r, int state);
+    vc_status check_done();
+    void fail_active(vc_status e);
+    void complete(Req& r);
+    void loop();
+};
+
+namespace {
+
+Server* get_server(vc_ctx* c) { return c->srv; }
+
+}  // namespace
+
+// The resident launch's fixed shape: degree arrays for serve_n_max
+// vertices in 16-bit entries, the library's worker plan, one registry root
+// per instance slot, and arena / pool regions for the instances' data.
+vc_status Server::plan() {
+    if (planned) return VC_OK;
+    const uint32_t n_max = c->opts.serve_n_max ? c->opts.serve_n_max : 4096u;
+    const uint32_t slots = c->opts.serve_slots ? c->opts.serve_slots : 4096u;
+    const uint32_t n_pad = std::max<uint32_t>(64u, (n_max + 63u) & ~63u);
+    LdsPlan lp;
+    uint32_t gwords = 0, w = 0;
+    vc_status pw = plan_workers(c, n_pad, deg_bytes, &lp, &gwords, &w);
+    if (pw) return pw;
+    // leave LDS on every CU for the root-step kernels of the side stream
+    if (lp.bytes > 128u * 1024u && gwords > 4096u) {
+        gwords -= std::min<uint32_t>(gwords - 4096u, (lp.bytes - 128u * 1024u + 3u) / 4u);
+        lp = lds_plan(n_pad, deg_bytes, gwords);
+    }
+    workers = w;
+    const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes + 16u;
+    const uint32_t depth = n_pad / 2u + 64u;
+    const uint32_t wl_cap = c->opts.worklist_cap ? c->opts.worklist_cap
+                                                 : std::max<uint32_t>(1024u, 4u * workers);
+    const uint32_t bm_words = ((n_pad + 31u) / 32u + 31u) & ~31u;
+    const uint64_t reg_cap = std::max<uint64_t>(
+        c->opts.registry_cap ? c->opts.registry_cap : (1u << 19), (uint64_t)slots + 64u);
+    host_cap = 32ull << 20;  // arena words for instance graphs
+    const uint64_t arena_words = host_cap + (32ull << 20);
+    pool_cap = 16ull << 20;
+    a = SearchArgs{};
+    a.n = n_max;
+    a.n_pad = n_pad;
+    a.slot_bytes = slot_bytes;
+    a.stack_depth = depth;
+    a.wl_cap = wl_cap;
+    a.reg_cap = (uint32_t)reg_cap;
+    a.bm_words = bm_words;
+    a.arena_words = arena_words;
+    a.gcache_words = gwords;
+    a.lds_L = lp.L;
+    a.lds_Q = lp.Q;
+    a.lds_R = lp.R;
+    a.lds_VB = lp.VB;
+    a.lds_PB = lp.PB;
+    a.lds_MK = lp.MK;
+    a.lds_G = lp.G;
+    a.lds_bytes = lp.bytes;
+    a.pvc = 0;
+    a.flags = c->opts.flags;
+    a.donate_slack = c->opts.donate_slack;
+    a.donate_min = c->opts.donate_min ? c->opts.donate_min : 48u;
+    a.watchdog_ticks =
+        (uint64_t)c->wall_khz * (c->opts.watchdog_ms ? c->opts.watchdog_ms : 120000u);
+    a.n_roots = slots;
+    a.batch = 1;
+    a.serve = 1;
+    a.inst_node_limit = c->opts.node_limit;
+    HIPCHK(ensure(stacks, (size_t)workers * depth * slot_bytes));
+    HIPCHK(ensure(wl_slots, (size_t)wl_cap * slot_bytes));
+    HIPCHK(ensure(wl_seq, 8ull * wl_cap));
+    HIPCHK(ensure(ctl, sizeof(Ctl)));
+    HIPCHK(ensure(reg, sizeof(RegEntry) * reg_cap));
+    HIPCHK(ensure(bitmaps, 4ull * bm_words * reg_cap));
+    HIPCHK(ensure(arena, 4ull * arena_words));
+    HIPCHK(ensure(st, 4ull * slots));
+    HIPCHK(ensure(nodes, 8ull * slots));
+    HIPCHK(ensure(kk, 4ull * slots));
+    HIPCHK(ensure(cancel, 4ull * slots));
+    HIPCHK(ensure(pool, 4ull * pool_cap));
+    a.stacks = (uint8_t*)stacks.p;
+    a.wl_slots = (uint8_t*)wl_slots.p;
+    a.wl_seq = (uint64_t*)wl_seq.p;
+    a.ctl = (Ctl*)ctl.p;
+    a.reg = (RegEntry*)reg.p;
+    a.bitmaps = (uint32_t*)bitmaps.p;
+    a.arena = (uint32_t*)arena.p;
+    a.inst_state = (int*)st.p;
+    a.inst_nodes = (uint64_t*)nodes.p;
+    a.inst_k = (const int*)kk.p;
+    a.inst_cancel = (const int*)cancel.p;
+    slot_req.assign(slots, nullptr);
+    h_state.assign(slots, 0);
+    h_nodes.assign(slots, 0);
+    planned = true;
+    return VC_OK;
+}
+
+// Root step buffers for a graph of n vertices and nnz entries (grown only
+// while no resident launch runs).
+vc_status Server::root_bufs(uint64_t n, uint64_t nnz, RootBufs* b) {
+    if (n > n_root || nnz > nnz_root) {
+        if (resident) return VC_EAGAIN;
+        n_root = std::max<uint64_t>(n, n_root);
+        nnz_root = std::max<uint64_t>(nnz, nnz_root);
+        const size_t n1 = n_root + 1;
+        HIPCHK(ensure(in_off, 4 * n1));
+        HIPCHK(ensure(in_col, 4 * std::max<uint64_t>(nnz_root, 1)));
+        HIPCHK(ensure(rdeg, 4 * n1));
+        HIPCHK(ensure(gdeg, 4 * n1));
+        HIPCHK(ensure(gin, n1));
+        HIPCHK(ensure(addf, n1));
+        HIPCHK(ensure(newly, n1));
+        HIPCHK(ensure(flags, 4 * (n1 + 1)));
+        HIPCHK(ensure(newid, 4 * (n1 + 1)));
+        HIPCHK(ensure(oldid, 4 * n1));
+        HIPCHK(ensure(kdeg, 4 * (n1 + 1)));
+        HIPCHK(ensure(koff, 4 * (n1 + 1)));
+        HIPCHK(ensure(kcol, 4 * std::max<uint64_t>(nnz_root, 1)));
+        HIPCHK(ensure(cover, 4 * n1));
+        HIPCHK(ensure(scan_tmp, 4 * (n1 / 2048 + 4)));
+        HIPCHK(ensure(ctr, CTR_COUNT * 4));
+        HIPCHK(ensure(hsum, 8));
+    }
+    b->rdeg = (uint32_t*)rdeg.p;
+    b->gdeg = (uint32_t*)gdeg.p;
+    b->gin = (uint8_t*)gin.p;
+    b->addf = (uint8_t*)addf.p;
+    b->newly = (uint8_t*)newly.p;
+    b->flags = (uint32_t*)flags.p;
+    b->newid = (uint32_t*)newid.p;
+    b->oldid = (uint32_t*)oldid.p;
+    b->kdeg = (uint32_t*)kdeg.p;
+    b->koff = (uint32_t*)koff.p;
+    b->kcol = kcol.p;
+    b->cover = (uint32_t*)cover.p;
+    b->scan_tmp = (uint32_t*)scan_tmp.p;
+    b->ctr = (uint32_t*)ctr.p;
+    b->hsum = (unsigned long long*)hsum.p;
+    return VC_OK;
+}
+
+vc_status Server::open_resident() {
+    if (resident) return VC_OK;
+    vc_status s0 = plan();
+    if (s0) return s0;
+    published = active = 0;
+    host_next = pool_next = 0;
+    std::fill(slot_req.begin(), slot_req.end(), nullptr);
+    HIPCHK(launch_serve_init(a, host_cap, ks));
+    HIPCHK(hipEventRecord(ready, ks));
+    HIPCHK(launch_search(a, deg_bytes, workers, ks));
+    HIPCHK(hipStreamWaitEvent(ss, ready, 0));
+    resident = true;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        resident_flag = true;
+    }
+    return VC_OK;
+}
+
+// Tell the resident launch that nothing more comes, wait for it to end.
+vc_status Server::close_resident() {
+    if (!resident) return VC_OK;
+    const int one = 1;
+    HIPCHK(hipMemcpyAsync(&a.ctl->closed, &one, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    HIPCHK(hipStreamSynchronize(ks));
+    Ctl h;
+    HIPCHK(hipMemcpy(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    resident = false;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        resident_flag = false;
+    }
+    if (h.err) {
+        fail_active((vc_status)h.err);
+        return VC_OK;
+    }
+    // every admitted instance has finished before the launch could end
+    return check_done();
+}
+
+void Server::complete(Req& r) {
+    std::lock_guard<std::mutex> g(mu);
+    if (r.done) return;
+    r.res.ms_latency = now_ms() - r.t_submit;
+    r.done = true;
+    if (pending) --pending;
+    cv.notify_all();
+}
+
+void Server::fail_active(vc_status e) {
+    for (auto& p : slot_req) {
+        if (p && p->admitted && !p->done) {
+            p->res.status = e;
+            complete(*p);
+        }
+        p = nullptr;
+    }
+    active = 0;
+}
+
+// Root steps of request r and, unless they decide it, its admission into
+// the resident launch.  Returns VC_EAGAIN (nothing done) when r has to wait.
+vc_status Server::start(Req& r) {
+    const double t0 = now_ms();
+    r.res.kind = r.kind;
+    r.res.n = r.n;
+    vc_csr g{r.n, r.nnz, r.off.data(), r.nnz ? (const void*)r.col.data() : nullptr, r.col_bytes, 0};
+    if (!(c->opts.flags & VC_OPT_VALIDATE_SKIP)) {
+        vc_status vs = validate_host(&g);
+        if (vs) {
+            r.res.status = vs;
+            return VC_OK;
+        }
+    }
+    if (r.n == 0 || r.nnz == 0) {
+        r.res.status = VC_OK;
+        r.res.size = 0;
+        r.res.yes = 1;
+        return VC_OK;
+    }
+    // no free instance slot in the running launch: wait for it to drain
+    if (resident && published >= a.n_roots) return VC_EAGAIN;
+    RootBufs b;
+    vc_status bs = root_bufs(r.n, r.nnz, &b);
+    if (bs) return bs;
+    RootGraph rg{r.n, r.nnz, (const uint32_t*)in_off.p, in_col.p, r.col_bytes};
+    HIPCHK(hipMemcpyAsync(in_off.p, r.off.data(), 4ull * (r.n + 1), hipMemcpyHostToDevice, ss));
+    HIPCHK(hipMemcpyAsync(in_col.p, r.col.data(), (size_t)r.col_bytes * r.nnz,
+                          hipMemcpyHostToDevice, ss));
+    hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, b.ctr, (uint64_t)CTR_COUNT);
+    HIPCHK(hipGetLastError());
+    HIPCHK(root_init(rg, b, ss));
+    uint32_t grounds = 0;
+    HIPCHK(root_greedy(rg, b, ss, &grounds));
+    HIPCHK(hipMemcpyAsync(&r.gsize, b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    auto list_to_host = [&](int improved, uint32_t np_, const uint32_t* bm) -> vc_status {
+        HIPCHK(root_cover(rg, b, np_, improved, bm, ss));
+        uint32_t cnt = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, b.newid + r.n, 4, hipMemcpyDeviceToHost, ss));
+        HIPCHK(hipStreamSynchronize(ss));
+        r.cover.resize(cnt);
+        if (cnt)
+            HIPCHK(hipMemcpyAsync(r.cover.data(), b.cover, 4ull * cnt, hipMemcpyDeviceToHost, ss));
+        HIPCHK(hipStreamSynchronize(ss));
+        r.res.cover_len = cnt;
+        return VC_OK;
+    };
+    const int pvc = r.kind == VC_PARAM;
+    const uint32_t kq = std::min<uint32_t>(r.k, 0x3FFFFFF0u);
+    if (pvc && r.gsize <= kq) {
+        r.res.yes = 1;
+        r.res.size = r.gsize;
+        return list_to_host(0, 0, nullptr);
+    }
+    const int best0 = pvc ? (int)kq + 1 : (int)r.gsize;
+    uint32_t rounds = 0;
+    HIPCHK(root_reduce(rg, b, best0, ss, 1u << 16, &rounds));
+    HIPCHK(hipMemcpyAsync(&r.sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    if ((int)r.sroot >= best0) {
+        if (pvc) return VC_OK;  // no
+        r.res.size = r.gsize;
+        r.res.yes = 1;
+        return list_to_host(0, 0, nullptr);
+    }
+    HIPCHK(root_induce_a(rg, b, ss));
+    uint32_t hdr[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&hdr[0], b.newid + r.n, 4, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipMemcpyAsync(&hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    r.np = hdr[0];
+    r.dmax = hdr[1];
+    r.kbest0 = best0 - (int)r.sroot;
+    if (r.np == 0) {
+        // the rules covered every edge
+        r.res.yes = 1;
+        vc_status ls = list_to_host(1, 0, nullptr);
+        r.res.size = r.res.cover_len;
+        return ls;
+    }
+    HIPCHK(root_induce_b(rg, b, r.np, 4, ss));
+    uint32_t nz = 0;
+    HIPCHK(hipMemcpyAsync(&nz, b.koff + r.np, 4, hipMemcpyDeviceToHost, ss));
+    HIPCHK(root_cover(rg, b, 0, 1, nullptr, ss));
+    HIPCHK(hipMemcpyAsync(&r.nforced, b.newid + r.n, 4, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    r.nnzp = nz;
+    // footprint in the running launch: the induced graph in the arena, the
+    // forced list, the greedy list and the id map in the pool
+    const uint64_t words = ((uint64_t)r.np + 1 + nz + 31) & ~31ull;
+    const uint64_t pwords = ((uint64_t)r.nforced + r.gsize + r.np + 31) & ~31ull;
+    vc_status ps0 = plan();
+    if (ps0) return ps0;
+    if (r.np > a.n || r.dmax > 65534u || words > host_cap || pwords > pool_cap) {
+        // too large for the resident search: solved alone by the plain
+        // path once the resident launch is closed
+        if (resident && active) return VC_EAGAIN;
+        vc_status cs = close_resident();
+        if (cs) return cs;
+        uint32_t size = 0, clen = 0;
+        int yes = 0;
+        r.cover.resize(r.n);
+        vc_status ps = solve_one(c, &g, pvc, r.k, &size, &yes, r.cover.data(), &clen);
+        r.res.status = ps;
+        r.res.size = pvc ? clen : size;
+        r.res.yes = pvc ? yes : 1;
+        r.res.cover_len = clen;
+        r.res.tree_nodes = c->last.tree_nodes;
+        r.cover.resize(clen);
+        return VC_OK;
+    }
+    if (resident && (host_next + words > host_cap || pool_next + pwords > pool_cap))
+        return VC_EAGAIN;  // room comes back when the launch drains
+    // keep what the cover needs later: the forced and greedy lists, the map
+    // back to the graph's ids (the forced list is in b.cover now)
+    vc_status os = open_resident();
+    if (os) return os;
+    uint32_t* pool_p = (uint32_t*)pool.p;
+    r.save_at = pool_next;
+    HIPCHK(hipMemcpyAsync(pool_p + r.save_at, b.cover, 4ull * r.nforced, hipMemcpyDeviceToDevice, ss));
+    HIPCHK(root_cover(rg, b, 0, 0, nullptr, ss));
+    HIPCHK(hipMemcpyAsync(pool_p + r.save_at + r.nforced, b.cover, 4ull * r.gsize,
+                          hipMemcpyDeviceToDevice, ss));
+    HIPCHK(hipMemcpyAsync(pool_p + r.save_at + r.nforced + r.gsize, b.oldid, 4ull * r.np,
+                          hipMemcpyDeviceToDevice, ss));
+    pool_next += pwords;
+    // the instance: graph into the arena, root entry, cleared bitmap and
+    // state, then the published count
+    const uint32_t slot = published;
+    const uint64_t g_at = host_next;
+    uint32_t* ar = a.arena + g_at;
+    HIPCHK(hipMemcpyAsync(ar, b.koff, 4ull * (r.np + 1), hipMemcpyDeviceToDevice, ss));
+    if (nz) HIPCHK(hipMemcpyAsync(ar + r.np + 1, b.kcol, 4ull * nz, hipMemcpyDeviceToDevice, ss));
+    host_next += words;
+    RegEntry e{};
+    e.best = r.kbest0;
+    e.live = 1;
+    e.up = -1;
+    e.cover_size = INF;
+    e.size = (int)r.np;
+    e.view = (int)slot;
+    e.vn = (int)r.np;
+    e.g_at = (uint32_t)g_at;
+    e.g_nnz = (int)nz;
+    const int zero = 0, kslot = pvc ? (int)kq - (int)r.sroot : -1;
+    const uint64_t zero64 = 0;
+    HIPCHK(hipMemcpyAsync(a.reg + slot, &e, sizeof(e), hipMemcpyHostToDevice, ss));
+    hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(256), 0, ss, a.bitmaps + (size_t)slot * a.bm_words,
+                       (uint64_t)a.bm_words);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(a.inst_state + slot, &zero, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipMemcpyAsync(a.inst_nodes + slot, &zero64, 8, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipMemcpyAsync((int*)a.inst_k + slot, &kslot, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipMemcpyAsync((int*)a.inst_cancel + slot, &zero, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    const uint32_t avail = slot + 1;
+    HIPCHK(hipMemcpyAsync(&a.ctl->inst_avail, &avail, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    published = avail;
+    ++active;
+    r.slot = slot;
+    r.admitted = true;
+    r.t_admit = now_ms();
+    r.res.ms_queued = r.t_admit - r.t_submit;
+    slot_req[slot] = nullptr;  // set by the caller (it holds the shared pointer)
+    (void)t0;
+    return VC_OK;
+}
+
+// The result of admitted request r from its root entry (state: its bits).
+vc_status Server::finish(Req& r, int state) {
+    RegEntry e;
+    HIPCHK(hipMemcpyAsync(&e, a.reg + r.slot, sizeof(e), hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    r.res.tree_nodes = h_nodes[r.slot];
+    if (r.canceled) {
+        r.res.status = VC_ECANCELED;
+        return VC_OK;
+    }
+    const int pvc = r.kind == VC_PARAM;
+    const int kslot = pvc ? (int)std::min<uint32_t>(r.k, 0x3FFFFFF0u) - (int)r.sroot : -1;
+    const bool attained = e.cover_size < INF && (pvc ? e.cover_size <= kslot : e.best < r.kbest0);
+    if (!attained) {
+        if ((state & INST_LIMIT)) {
+            r.res.status = VC_ETIMEDOUT;
+            if (pvc) return VC_OK;
+        }
+        if (pvc) return VC_OK;  // no
+        // nothing below the greedy bound: the greedy cover is minimum
+        r.res.size = r.gsize;
+        r.res.yes = 1;
+        r.cover.resize(r.gsize);
+        const uint32_t* gl = (const uint32_t*)pool.p + r.save_at + r.nforced;
+        if (r.gsize)
+            HIPCHK(hipMemcpyAsync(r.cover.data(), gl, 4ull * r.gsize, hipMemcpyDeviceToHost, ss));
+        HIPCHK(hipStreamSynchronize(ss));
+        r.res.cover_len = r.gsize;
+        return VC_OK;
+    }
+    if (!pvc && (state & INST_LIMIT)) r.res.status = VC_ETIMEDOUT;
+    // cover = forced vertices + the root bitmap mapped back (ascending)
+    RootBufs b;
+    vc_status bs = root_bufs(r.n, 0, &b);
+    if (bs) return bs;
+    const uint32_t* pl = (const uint32_t*)pool.p + r.save_at;
+    hipLaunchKernelGGL(k_srv_zero, dim3(grid_of(r.n + 1)), dim3(256), 0, ss, b.flags,
+                       (uint64_t)r.n + 1);
+    if (r.nforced)
+        hipLaunchKernelGGL(k_srv_mark_list, dim3(grid_of(r.nforced)), dim3(256), 0, ss, pl,
+                           r.nforced, b.flags);
+    hipLaunchKernelGGL(k_srv_mark_bits, dim3(grid_of(r.np)), dim3(256), 0, ss, r.np,
+                       pl + r.nforced + r.gsize, a.bitmaps + (size_t)r.slot * a.bm_words, b.flags);
+    HIPCHK(hipGetLastError());
+    HIPCHK(scan_u32(b.flags, r.n, b.newid, b.scan_tmp, ss));
+    hipLaunchKernelGGL(k_srv_emit, dim3(grid_of(r.n)), dim3(256), 0, ss, r.n, b.flags, b.newid,
+                       b.cover);
+    HIPCHK(hipGetLastError());
+    uint32_t cnt = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, b.newid + r.n, 4, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    r.cover.resize(cnt);
+    if (cnt) HIPCHK(hipMemcpyAsync(r.cover.data(), b.cover, 4ull * cnt, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    r.res.cover_len = cnt;
+    r.res.yes = 1;
+    r.res.size = pvc ? cnt : r.sroot + (uint32_t)e.best;
+    // internal invariant: an MVC cover has exactly the reported size
+    if (!pvc && cnt != r.res.size && !(state & INST_LIMIT)) r.res.status = VC_EDEVICE;
+    return VC_OK;
+}
+
+// Read the instances' state; finish those that are answered.
+vc_status Server::check_done() {
+    if (!published || !active) return VC_OK;
+    HIPCHK(hipMemcpyAsync(h_state.data(), a.inst_state, 4ull * published, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipMemcpyAsync(h_nodes.data(), a.inst_nodes, 8ull * published, hipMemcpyDeviceToHost, ss));
+    int ctl_done[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(ctl_done, &a.ctl->done, 8, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    for (uint32_t i = 0; i < published; ++i) {
+        auto& p = slot_req[i];
+        if (!p || p->done) continue;
+        const int s = h_state[i];
+        const bool answered = (s & INST_FIN) || (p->kind == VC_PARAM && (s & INST_STOP) &&
+                                                 !(s & INST_LIMIT) && !p->canceled);
+        if (!answered) {
+            if (p->canceled && !p->cancel_sent) {
+                const int one = 1;
+                HIPCHK(hipMemcpyAsync((int*)a.inst_cancel + i, &one, 4, hipMemcpyHostToDevice, ss));
+                HIPCHK(hipStreamSynchronize(ss));
+                p->cancel_sent = true;
+            }
+            continue;
+        }
+        vc_status fs = finish(*p, s);
+        if (fs) p->res.status = fs;
+        if (s & INST_FIN) {
+            --active;
+            auto keep = p;
+            p = nullptr;
+            if (!keep->done) complete(*keep);
+        } else if (!p->done) {
+            complete(*p);  // a PVC yes: answered while its nodes drain
+        }
+    }
+    // a FIN that arrived for an already answered PVC instance frees its slot
+    for (uint32_t i = 0; i < published; ++i) {
+        auto& p = slot_req[i];
+        if (p && p->done && (h_state[i] & INST_FIN)) {
+            --active;
+            p = nullptr;
+        }
+    }
+    if (ctl_done[1]) {
+        // the resident launch stopped on an error
+        const vc_status e = (vc_status)ctl_done[1];
+        HIPCHK(hipStreamSynchronize(ks));
+        resident = false;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            resident_flag = false;
+        }
+        fail_active(e);
+    }
+    return VC_OK;
+}
+
+void Server::loop() {
+    if (hipSetDevice(c->device) != hipSuccess) {
+        std::lock_guard<std::mutex> g(mu);
+        stop = true;
+    }
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> g(mu);
+            while (!incoming.empty()) {
+                queue.push_back(incoming.front());
+                incoming.pop_front();
+            }
+            if (stop && queue.empty() && active == 0) break;
+        }
+        bool progress = false;
+        if (resident && active) {
+            if (check_done()) fail_active(VC_EDEVICE);
+        }
+        if (!queue.empty()) {
+            auto r = queue.front();
+            if (r->canceled) {
+                queue.pop_front();
+                r->res.status = VC_ECANCELED;
+                complete(*r);
+                progress = true;
+            } else {
+                const vc_status s = start(*r);
+                if (s == VC_EAGAIN) {
+                    // waits for room; a launch with nothing active is closed
+                    // so the next one starts empty
+                    if (resident && active == 0) {
+                        close_resident();
+                        progress = true;
+                    }
+                } else {
+                    queue.pop_front();
+                    progress = true;
+                    if (s) r->res.status = s;
+                    if (r->admitted && !s) slot_req[r->slot] = r;
+                    else complete(*r);
+                }
+            }
+        }
+        if (resident && active == 0 && queue.empty()) {
+            // nothing left: end the resident launch after a short grace
+            if (idle_since == 0) idle_since = now_ms();
+            if (now_ms() - idle_since > 2.0 || stop) {
+                close_resident();
+                idle_since = 0;
+            }
+        } else {
+            idle_since = 0;
+        }
+        if (!progress) {
+            std::unique_lock<std::mutex> g(mu);
+            cv.wait_for(g, std::chrono::microseconds(50), [&] { return !incoming.empty() || stop; });
+        }
+    }
+    close_resident();
+}
+
+bool server_busy(vc_ctx* c) {
+    Server* s = get_server(c);
+    if (!s) return false;
+    std::lock_guard<std::mutex> g(s->mu);
+    return s->pending > 0 || s->resident_flag;
+}
+
+void server_shutdown(vc_ctx* c) {
+    Server* s = get_server(c);
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        // requests not yet started are cancelled
+        for (auto& r : s->incoming) r->canceled = true;
+        s->cv.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    DevBuf* bufs[] = {&s->in_off, &s->in_col, &s->rdeg,  &s->gdeg,    &s->gin,     &s->addf,
+                      &s->newly,  &s->flags,  &s->newid, &s->oldid,   &s->kdeg,    &s->koff,
+                      &s->kcol,   &s->cover,  &s->scan_tmp, &s->ctr,  &s->hsum,    &s->pool,
+                      &s->stacks, &s->wl_slots, &s->wl_seq, &s->ctl,  &s->reg,     &s->bitmaps,
+                      &s->arena,  &s->st,     &s->nodes, &s->kk,      &s->cancel};
+    for (DevBuf* b : bufs)
+        if (b->p) hipFree(b->p);
+    if (s->ready) hipEventDestroy(s->ready);
+    if (s->ss) hipStreamDestroy(s->ss);
+    if (s->ks) hipStreamDestroy(s->ks);
+    delete s;
+    c->srv = nullptr;
+}
+
+}  // namespace vc
+
+using namespace vc;
+
+extern "C" {
+
+vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* ticket) {
+    if (!c || !ticket) return VC_EINVAL;
+    if (kind != VC_MIN && kind != VC_PARAM) return VC_EINVAL;
+    vc_status st = check_args(g);
+    if (st) return st;
+    if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    auto r = std::make_shared<Req>();
+    r->kind = kind;
+    r->k = k;
+    r->n = g->n;
+    r->nnz = g->nnz;
+    r->col_bytes = g->col_bytes;
+    r->off.resize((size_t)g->n + 1);
+    r->col.resize((size_t)g->col_bytes * g->nnz);
+    // the request keeps its own copy: the caller may free the graph now
+    if (g->flags & VC_CSR_DEVICE) {
+        if (hipMemcpy(r->off.data(), g->offsets, 4ull * (g->n + 1), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return VC_EDEVICE;
+        if (g->nnz && hipMemcpy(r->col.data(), g->cols, r->col.size(), hipMemcpyDeviceToHost) !=
+                          hipSuccess)
+            return VC_EDEVICE;
+    } else {
+        memcpy(r->off.data(), g->offsets, 4ull * (g->n + 1));
+        if (g->nnz) memcpy(r->col.data(), g->cols, r->col.size());
+    }
+    r->t_submit = now_ms();
+    static std::mutex create_mu;
+    {
+        std::lock_guard<std::mutex> cg(create_mu);
+        if (!c->srv) {
+            Server* s = new (std::nothrow) Server();
+            if (!s) return VC_ENOMEM;
+            s->c = c;
+            if (hipStreamCreateWithFlags(&s->ss, hipStreamNonBlocking) != hipSuccess ||
+                hipStreamCreateWithFlags(&s->ks, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess) {
+                delete s;
+                return VC_EDEVICE;
+            }
+            c->srv = s;
+            s->th = std::thread([s] { s->loop(); });
+        }
+    }
+    Server* s = c->srv;
+    std::lock_guard<std::mutex> gl(s->mu);
+    if (s->stop) return VC_ECANCELED;
+    r->ticket = s->next_ticket++;
+    s->table[r->ticket] = r;
+    s->incoming.push_back(r);
+    ++s->pending;
+    *ticket = r->ticket;
+    s->cv.notify_all();
+    return VC_OK;
+}
+
+vc_status vc_poll(vc_ctx* c, uint64_t ticket, vc_result* out, uint32_t* cover) {
+    if (!c || !out) return VC_EINVAL;
+    Server* s = c->srv;
+    if (!s) return VC_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->table.find(ticket);
+    if (it == s->table.end()) return VC_EINVAL;
+    Req& r = *it->second;
+    if (!r.done) return VC_EAGAIN;
+    *out = r.res;
+    if (cover && r.res.cover_len) memcpy(cover, r.cover.data(), 4ull * r.res.cover_len);
+    const vc_status rs = r.res.status == VC_ECANCELED ? VC_ECANCELED : VC_OK;
+    s->table.erase(it);
+    return rs;
+}
+
+vc_status vc_cancel(vc_ctx* c, uint64_t ticket) {
+    if (!c) return VC_EINVAL;
+    Server* s = c->srv;
+    if (!s) return VC_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->table.find(ticket);
+    if (it == s->table.end()) return VC_EINVAL;
+    it->second->canceled = true;
+    s->cv.notify_all();
+    return VC_OK;
+}
+
+}  // extern "C"

@@ -277,7 +277,11 @@ def chung_lu_planted(n: int, m: int, gamma: float, s_size: int, seed: int,
     (from V \\ S when ``bipartite``) proportional to w; self-pairs and repeats
     are rejected until exactly m distinct edges exist, so every edge has an
     endpoint in S.  i0 is the smallest offset (found by bisection) for which
-    the heaviest vertex's expected degree is at most sqrt(2m).
+    the heaviest vertex's expected degree is at most sqrt(2m) (if no offset
+    up to 1e9 meets that cap, i0 = that bound: nearly flat weights).  When three
+    rounds of weighted draws in a row add under 1% of the missing edges (a
+    small instance close to saturating S x V), the remaining edges are drawn
+    uniformly from S x V.
     """
     r = rng(seed)
     cap = math.sqrt(2.0 * m)
@@ -289,14 +293,18 @@ def chung_lu_planted(n: int, m: int, gamma: float, s_size: int, seed: int,
         return m * w[0] / ws + (0.0 if bipartite else m * w[0] / wv)
 
     lo, hi = 0.0, 1.0
-    while maxdeg(hi) > cap:
+    while maxdeg(hi) > cap and hi < 1e9:
         hi *= 2.0
-    for _ in range(60):
-        mid = 0.5 * (lo + hi)
-        if maxdeg(mid) > cap:
-            lo = mid
-        else:
-            hi = mid
+    cap_met = maxdeg(hi) <= cap
+    if cap_met:
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            if maxdeg(mid) > cap:
+                lo = mid
+            else:
+                hi = mid
+    # (a small instance can need more than sqrt(2m) per vertex of S on
+    # average; then the flattest weights tried, i0 = hi, are used)
     i0 = hi
     w = _chung_lu_weights(n, gamma, i0)
     cs = np.cumsum(w[:s_size])
@@ -310,10 +318,22 @@ def chung_lu_planted(n: int, m: int, gamma: float, s_size: int, seed: int,
     cv /= cv[-1]
     keys = np.zeros(0, np.int64)
     need = m
+    pairs = s_size * (s_size - 1) // 2 + s_size * (n - s_size) if not bipartite \
+        else s_size * (n - s_size)
+    if m > pairs:
+        raise ValueError(f"{m} edges cannot all touch {s_size} of {n} vertices")
+    stalls = 0
     while True:
         batch = int(need * 1.25) + 1024
-        u = np.searchsorted(cs, r.random(batch), side="right").astype(np.int64)
-        v = (np.searchsorted(cv, r.random(batch), side="right") + base).astype(np.int64)
+        if stalls < 3:
+            u = np.searchsorted(cs, r.random(batch), side="right").astype(np.int64)
+            v = (np.searchsorted(cv, r.random(batch), side="right") + base).astype(np.int64)
+        else:
+            # the weighted draws have stopped finding new pairs (a small,
+            # dense instance): the rest of the edges are drawn uniformly
+            # over S x V, which keeps S a cover
+            u = r.integers(0, s_size, batch).astype(np.int64)
+            v = r.integers(base, n, batch).astype(np.int64)
         np.minimum(u, s_size - 1, out=u)
         np.minimum(v, n - 1, out=v)
         ok = u != v
@@ -325,11 +345,13 @@ def chung_lu_planted(n: int, m: int, gamma: float, s_size: int, seed: int,
         if keys.size >= m:
             keys = keys[:m]
             break
+        stalls = stalls + 1 if (m - keys.size) > 0.99 * need else 0
         need = m - keys.size
     a, b = keys // n, keys % n
     perm = r.permutation(n)
     S = np.sort(perm[np.arange(s_size)])
-    meta = {"gamma": gamma, "i0": i0, "planted_size": s_size, "bipartite": bipartite}
+    meta = {"gamma": gamma, "i0": i0, "planted_size": s_size, "bipartite": bipartite,
+            "degree_cap_met": bool(cap_met), "uniform_fill": stalls >= 3}
     return from_edges(n, perm[a], perm[b], name or f"chung_lu(n={n},m={m})",
                       col_bytes, S, meta)
 

@@ -24,12 +24,13 @@ VC_OPT_NO_COMPONENTS = 1
 VC_OPT_NO_LOAD_BALANCE = 2
 VC_OPT_VALIDATE_SKIP = 4
 VC_OPT_NO_GRAPH = 8
+VC_MIN, VC_PARAM = 0, 1
 
 CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]
 
 EXPORTS = ["vc_ctx_create", "vc_ctx_destroy", "vc_validate", "vc_min",
-           "vc_param", "vc_min_batch", "vc_param_batch", "vc_last_stats",
-           "vc_status_str"]
+           "vc_param", "vc_min_batch", "vc_param_batch", "vc_submit", "vc_poll",
+           "vc_cancel", "vc_last_stats", "vc_status_str"]
 
 
 class vc_csr(ctypes.Structure):
@@ -51,7 +52,16 @@ class vc_opts(ctypes.Structure):
                 ("worklist_cap", ctypes.c_uint32), ("registry_cap", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("node_limit", ctypes.c_uint64),
                 ("flags", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
-                ("donate_min", ctypes.c_uint32), ("gcache_words", ctypes.c_uint32)]
+                ("donate_min", ctypes.c_uint32), ("gcache_words", ctypes.c_uint32),
+                ("serve_n_max", ctypes.c_uint32), ("serve_slots", ctypes.c_uint32)]
+
+
+class vc_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("size", ctypes.c_uint32), ("yes", ctypes.c_int32),
+                ("cover_len", ctypes.c_uint32), ("n", ctypes.c_uint32),
+                ("tree_nodes", ctypes.c_uint64), ("ms_queued", ctypes.c_double),
+                ("ms_latency", ctypes.c_double)]
 
 
 class vc_stats(ctypes.Structure):
@@ -117,6 +127,13 @@ def load():
     lib.vc_param_batch.restype = ctypes.c_int
     lib.vc_param_batch.argtypes = [p, ctypes.POINTER(vc_batch), u32p,
                                    ctypes.POINTER(ctypes.c_int), i32p, u32p, u64p]
+    lib.vc_submit.restype = ctypes.c_int
+    lib.vc_submit.argtypes = [p, ctypes.POINTER(vc_csr), ctypes.c_int, ctypes.c_uint32,
+                              u64p]
+    lib.vc_poll.restype = ctypes.c_int
+    lib.vc_poll.argtypes = [p, ctypes.c_uint64, ctypes.POINTER(vc_result), u32p]
+    lib.vc_cancel.restype = ctypes.c_int
+    lib.vc_cancel.argtypes = [p, ctypes.c_uint64]
     lib.vc_last_stats.restype = ctypes.c_int
     lib.vc_last_stats.argtypes = [p, ctypes.POINTER(vc_stats)]
     lib.vc_status_str.restype = ctypes.c_char_p
@@ -247,11 +264,12 @@ class Solver:
                  donate_slack: int = 0, worklist_cap: int = 0,
                  registry_cap: int = 0, hbm_budget: int = 0,
                  node_limit: int = 0, flags: int = 0, watchdog_ms: int = 0,
-                 donate_min: int = 0, gcache_words: int = 0):
+                 donate_min: int = 0, gcache_words: int = 0, serve_n_max: int = 0,
+                 serve_slots: int = 0):
         lib = load()
         self._opts = vc_opts(workers, donate_slack, worklist_cap, registry_cap,
                              hbm_budget, node_limit, flags, watchdog_ms,
-                             donate_min, gcache_words)
+                             donate_min, gcache_words, serve_n_max, serve_slots)
         h = ctypes.c_void_p()
         st = lib.vc_ctx_create(int(device), stream, ctypes.byref(self._opts),
                                ctypes.byref(h))
@@ -317,6 +335,42 @@ class Solver:
         _check(st, "vc_param")
         return Result(None, bool(yes.value), cov[:clen.value].copy(), self.stats())
 
+
+    def submit(self, g, kind: int = VC_MIN, k: int = 0) -> int:
+        """vc_submit: returns the ticket (the graph is copied)."""
+        c, keep = self._csr(g)
+        t = ctypes.c_uint64(0)
+        _check(load().vc_submit(self._h, ctypes.byref(c), int(kind), int(k),
+                                ctypes.byref(t)), "vc_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int, n: int):
+        """vc_poll: None while pending, else (vc_result fields dict, cover).
+        Raises VCError for a cancelled or unknown ticket."""
+        r = vc_result()
+        cov = np.zeros(max(int(n), 1), np.uint32)
+        st = load().vc_poll(self._h, int(ticket), ctypes.byref(r),
+                            cov.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        if st == VC_EAGAIN:
+            return None
+        _check(st, "vc_poll")
+        out = {f: getattr(r, f) for f, _ in vc_result._fields_}
+        return out, cov[:r.cover_len].copy()
+
+    def cancel(self, ticket: int):
+        _check(load().vc_cancel(self._h, int(ticket)), "vc_cancel")
+
+    def wait(self, ticket: int, n: int, timeout_s: float = 120.0):
+        """Poll until the request is answered (or raise after timeout_s)."""
+        import time
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket, n)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"request {ticket} still pending")
+            time.sleep(0.0002)
 
     def mvc_batch(self, batch, want_cover: bool = True) -> BatchResult:
         """vc_min_batch over a Batch (or a list of graphs, packed here)."""

@@ -26,8 +26,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ["vc_ctx_create", "vc_ctx_destroy", "vc_min", "vc_param",
-              "vc_min_batch", "vc_param_batch", "vc_validate", "vc_last_stats",
-              "vc_status_str"]:
+              "vc_min_batch", "vc_param_batch", "vc_submit", "vc_poll", "vc_cancel",
+              "vc_validate", "vc_last_stats", "vc_status_str"]:
         assert f in names
 
 
@@ -48,6 +48,7 @@ def test_struct_layout_matches_header(tmp_path, libvc):
         "vc_opts": [f for f, _ in vc.vc_opts._fields_],
         "vc_stats": [f for f, _ in vc.vc_stats._fields_],
         "vc_batch": [f for f, _ in vc.vc_batch._fields_],
+        "vc_result": [f for f, _ in vc.vc_result._fields_],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vc.h"',
              "int main(void) {"]
@@ -63,7 +64,8 @@ def test_struct_layout_matches_header(tmp_path, libvc):
     got = dict(l.split() for l in subprocess.run(
         [str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
     for s, cls in [("vc_csr", vc.vc_csr), ("vc_opts", vc.vc_opts),
-                   ("vc_stats", vc.vc_stats), ("vc_batch", vc.vc_batch)]:
+                   ("vc_stats", vc.vc_stats), ("vc_batch", vc.vc_batch),
+                   ("vc_result", vc.vc_result)]:
         assert int(got[s]) == ctypes.sizeof(cls), s
         for f, _ in cls._fields_:
             assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
@@ -140,3 +142,13 @@ def test_batch_packing_layout():
         assert np.array_equal(b.offsets[ob:ob + g.n + 1], g.offsets)
         assert int(b.offsets[ob]) == 0 and int(b.offsets[ob + g.n]) == g.nnz
         assert np.array_equal(b.cols[cb:cb + g.nnz], np.asarray(g.cols))
+
+
+def test_serving_entry_points_reject_missing_context(libvc):
+    g = gg.petersen()
+    c, keep = vc.host_csr(g)
+    t = ctypes.c_uint64(0)
+    assert libvc.vc_submit(None, ctypes.byref(c), vc.VC_MIN, 0, ctypes.byref(t)) == vc.VC_EINVAL
+    r = vc.vc_result()
+    assert libvc.vc_poll(None, 1, ctypes.byref(r), None) == vc.VC_EINVAL
+    assert libvc.vc_cancel(None, 1) == vc.VC_EINVAL

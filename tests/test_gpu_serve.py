@@ -1,0 +1,120 @@
+"""Serving through the C ABI (vc_submit / vc_poll / vc_cancel).
+
+Requests of different kinds and sizes are submitted together so that they
+are admitted into the resident search while others run; every answer must
+equal the oracle's and the one the same request gets alone (exact integers),
+and every cover is checked on every edge.
+"""
+import time
+
+import pytest
+
+from paper_2512_18334_amd import graphgen as gg
+from paper_2512_18334_amd import vc
+from tests.helpers import assert_cover
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver(libvc):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    s = vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000)
+    yield s
+    s.close()
+
+
+def request_mix():
+    """(graph, kind, k) in arrival order: the served-stream recipe at
+    reduced sizes plus small exact cases."""
+    reqs = []
+    for i, r in enumerate(gg.config5_stream(count=16, n_hi=20_000)):
+        reqs.append((r["graph"], vc.VC_MIN if r["kind"] == "min" else vc.VC_PARAM, r["k"]))
+    for s in range(1, 13):
+        reqs.append((gg.config1_gnp60(s), vc.VC_MIN, 0))
+    reqs.append((gg.config2_blocks_hubs(seed=50, nblocks=5, bsize=40, nhubs=3, per_block=10),
+                 vc.VC_MIN, 0))
+    reqs.append((gg.petersen(), vc.VC_PARAM, 5))
+    reqs.append((gg.petersen(), vc.VC_PARAM, 6))
+    reqs.append((gg.fig1_tree(), vc.VC_MIN, 0))
+    reqs.append((gg.from_edges(4, [], []), vc.VC_MIN, 0))
+    return reqs
+
+
+def wait_idle_then(fn, timeout_s=30.0):
+    """Run a blocking solve once the server has nothing in flight."""
+    t0 = time.perf_counter()
+    while True:
+        try:
+            return fn()
+        except vc.VCError as e:
+            if e.status != vc.VC_EAGAIN or time.perf_counter() - t0 > timeout_s:
+                raise
+            time.sleep(0.005)
+
+
+def test_served_mix_matches_oracle_and_alone(solver, orc):
+    reqs = request_mix()
+    tickets = [solver.submit(g, kind, k) for g, kind, k in reqs]
+    results = [solver.wait(t, g.n) for t, (g, _, _) in zip(tickets, reqs)]
+    for (g, kind, k), (res, cov) in zip(reqs, results):
+        assert res["status"] == vc.VC_OK, (g.name, res)
+        mvc = orc.mvc(g)["size"]
+        if kind == vc.VC_MIN:
+            assert res["size"] == mvc, (g.name, res["size"], mvc)
+            assert_cover(g, cov, size=mvc)
+        else:
+            assert bool(res["yes"]) == (mvc <= k), (g.name, k, mvc)
+            if res["yes"]:
+                assert_cover(g, cov, at_most=k)
+            else:
+                assert cov.size == 0
+    # the same requests alone, one blocking solve each
+    for (g, kind, k), (res, _) in zip(reqs, results):
+        if kind == vc.VC_MIN:
+            alone = wait_idle_then(lambda: solver.mvc(g)).size
+            assert res["size"] == alone
+        else:
+            alone = wait_idle_then(lambda: solver.pvc(g, k)).yes
+            assert bool(res["yes"]) == alone
+
+
+def test_served_requests_overlap_in_one_launch(solver, orc):
+    """Requests submitted back to back are in the resident search together:
+    at least one is admitted while another is still unanswered."""
+    gs = [gg.config2_blocks_hubs(seed=60 + s, nblocks=12, bsize=64, nhubs=4, per_block=16)
+          for s in range(6)]
+    tickets = [solver.submit(g) for g in gs]
+    results = [solver.wait(t, g.n) for t, g in zip(tickets, gs)]
+    for g, (res, cov) in zip(gs, results):
+        e = orc.mvc(g)["size"]
+        assert res["size"] == e
+        assert_cover(g, cov, size=e)
+    lat = [r["ms_latency"] for r, _ in results]
+    queued = sorted(r["ms_queued"] for r, _ in results)
+    # a second request was admitted before the first answer was ready
+    assert queued[1] < min(lat), (queued, lat)
+
+
+def test_cancel_and_unknown_ticket(solver):
+    g = gg.gnp(220, 0.09, 4242)  # far too hard to finish quickly
+    t = solver.submit(g)
+    solver.cancel(t)
+    with pytest.raises(vc.VCError) as e:
+        solver.wait(t, g.n, timeout_s=60)
+    assert e.value.status == vc.VC_ECANCELED
+    with pytest.raises(vc.VCError) as e:
+        solver.poll(t, g.n)
+    assert e.value.status == vc.VC_EINVAL
+
+
+def test_device_graph_submission(solver, orc):
+    g = gg.config1_gnp60(77)
+    dg = vc.DeviceGraph.from_graph(g)
+    t = solver.submit(dg)
+    del dg  # the request holds its own copy
+    res, cov = solver.wait(t, g.n)
+    e = orc.mvc(g)["size"]
+    assert res["size"] == e
+    assert_cover(g, cov, size=e)
