@@ -1,14 +1,21 @@
 #!/usr/bin/env python3
-"""Benchmark: exact MVC of the component-splitting blocks-and-hubs graph on
-one MI355X (time-to-solution and search-nodes/s), with the HBM-roofline view
-of the persistent search kernel and the CPU oracle timed beside it.
+"""Benchmark of the exact vertex cover search on one MI355X.
 
-Workload (seeded, synthetic): 20 uniform random 3-regular blocks of 96
-vertices plus 8 hubs, each joined to 30 random vertices of every block;
-n = 1,928, m = 7,680, CSR uint32 offsets / uint32 cols, resident in HBM
-before the timed region.  One step = one vc_min call on it (validation,
-degrees, greedy bound, root reduction, induce, search, cover assembly and
-the cover copied back to the host).
+Default workload (the headline line): exact MVC of the component-splitting
+blocks-and-hubs graph -- 20 uniform random 3-regular blocks of 96 vertices
+plus 8 hubs, each joined to 30 random vertices of every block; n = 1,928,
+m = 7,680, CSR uint32 resident in HBM before the timed region.  One step is
+one vc_min call on it (validation, degrees, greedy bound, root reduction,
+induce, search, cover assembly, the cover copied back).  The line carries
+the HBM-roofline view of the persistent search kernel and the CPU oracle
+timed beside it.
+
+--workload batch: batched graphs/s on the uneven 4,096-graph batch (one
+captured launch per step, a per-instance node limit), with the plain
+one-graph-per-launch solver on a prefix of the batch for comparison.
+--workload serve: a served stream of mixed MVC/PVC requests with Poisson
+arrivals; p50/p99 latency and solves/s, against the plain solver serving
+the same arrivals first come first served.
 
 Prints one JSON line.  Only one GPU is supported: --gpus N with N > 1 exits.
 """
@@ -67,33 +74,19 @@ def cpu_baseline(g, budget_s: float):
                       f"{el / reps * 1e3:.1f} ms per solve)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="after the timed steps, copy this many MiB device to "
-                         "device once: a kernel of known traffic that scales "
-                         "the HBM byte counters of a profiler run")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the search shards across GPUs only by instance, see the design notes",
-              file=sys.stderr)
-        sys.exit(2)
+def roofline(stats_list, search_ms):
+    """HBM view of the search kernel: algorithmic bytes per launch (node
+    slots written and read back once, the root slot, registry entries,
+    cover bitmaps and per-component graphs, all counted on the device) over
+    the kernel's time."""
+    alg_bytes = sum(2 * s["bytes_nodes"] + s["slot_bytes"] + s["bytes_registry"]
+                    for s in stats_list) / len(stats_list)
+    achieved = alg_bytes / (search_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(alg_bytes)}
 
-    import torch
-    from paper_2512_18334_amd import graphgen as gg
-    from paper_2512_18334_amd import vc
 
-    if not os.path.exists(vc.LIB_PATH):
-        import __graft_entry__
-        __graft_entry__.build()
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-
+def bench_blocks_hubs(args, torch, gg, vc):
     g = gg.config2_blocks_hubs()
     dg = vc.DeviceGraph.from_graph(g, "cuda:0")
     torch.cuda.synchronize()
@@ -114,14 +107,7 @@ def main():
     nodes = sum(s["tree_nodes"] for s in stats)
     ms_step = el * 1e3 / args.steps
     search_ms = sum(s["ms_search"] for s in stats) / len(stats)
-    # algorithmic HBM bytes of one search launch: every node written to a
-    # slot (header, the degree array of its graph view, trailer) is read back
-    # once, the root node is read once, and the registry entries, cover
-    # bitmaps and per-component graphs are written (device counters)
     s0 = stats[-1]
-    alg_bytes = sum(2 * s["bytes_nodes"] + s["slot_bytes"] + s["bytes_registry"]
-                    for s in stats) / len(stats)
-    achieved = alg_bytes / (search_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": nodes / el,
@@ -142,9 +128,7 @@ def main():
                    "deg_bytes": s0["deg_bytes"],
                    "component_branches_per_solve":
                        sum(s["component_branches"] for s in stats) / len(stats)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(alg_bytes)},
+        "roofline": roofline(stats, search_ms),
     }
     if args.copy_mib:
         src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda:0")
@@ -156,6 +140,190 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
     solver.close()
+    return out
+
+
+def bench_batch(args, torch, gg, vc):
+    """Batched graphs/s on the uneven 4096-graph batch: one captured launch
+    per step, each instance capped at --node-limit tree nodes; the plain
+    one-graph-per-launch solver runs a prefix of the batch beside it."""
+    import numpy as np
+    gs = gg.config4_batch(count=args.batch_count)
+    b = vc.Batch.from_graphs(gs).to_device("cuda:0")
+    opts = {}
+    if args.autotune:
+        from paper_2512_18334_amd import autotune
+        sample = vc.Batch.from_graphs(gs[:min(512, len(gs))]).to_device("cuda:0")
+        tuned = autotune.tune_batch(sample, node_limit=args.node_limit, cache=args.tune_cache,
+                                    log=lambda m: print(m, file=sys.stderr, flush=True))
+        opts = tuned["opts"]
+    solver = vc.Solver(0, node_limit=args.node_limit, watchdog_ms=120_000, **opts)
+    for _ in range(args.warmup):
+        solver.mvc_batch(b, want_cover=False)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = solver.mvc_batch(b, want_cover=False)
+        stats.append(r.stats)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    capped = int((r.status != vc.VC_OK).sum())
+    # plain per-graph solver on a prefix, same node limit
+    nplain = min(args.plain_count, len(gs))
+    dgs = [vc.DeviceGraph.from_graph(g, "cuda:0") for g in gs[:nplain]]
+    agree = checked = 0
+    with vc.Solver(0, node_limit=args.node_limit, watchdog_ms=120_000, **opts) as plain:
+        t1 = time.perf_counter()
+        psz = []
+        for dg in dgs:
+            try:
+                psz.append(plain.mvc(dg, want_cover=False).size)
+            except vc.VCError as e:
+                if e.status != vc.VC_ETIMEDOUT:
+                    raise
+                psz.append(None)
+        pel = time.perf_counter() - t1
+    for i, ps in enumerate(psz):
+        if ps is not None and r.status[i] == vc.VC_OK:
+            checked += 1
+            agree += int(ps == int(r.sizes[i]))
+    search_ms = sum(s["ms_search"] for s in stats) / len(stats)
+    out = {
+        "metric": METRIC, "value": len(gs) * args.steps / el, "unit": "graphs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"mvc_batch_{len(gs)}_uneven", "count": len(gs),
+                   "node_limit_per_instance": args.node_limit,
+                   "instances_at_limit": capped,
+                   "tree_nodes_per_step": stats[-1]["tree_nodes"],
+                   "search_nodes_per_s": stats[-1]["tree_nodes"] / (search_ms * 1e-3),
+                   "plain_graphs_per_s": nplain / pel, "plain_prefix": nplain,
+                   "plain_agree": f"{agree}/{checked}", "opts": opts},
+        "roofline": roofline(stats, search_ms),
+    }
+    solver.close()
+    return out
+
+
+def bench_serve(args, torch, gg, vc):
+    """Served stream: Poisson arrivals at --rate of mixed MVC/PVC requests;
+    p50/p99 latency and solves/s, against the plain per-graph solver serving
+    the same arrivals first come first served (its queueing computed from
+    its measured service times)."""
+    import numpy as np
+    reqs = gg.config5_stream(count=args.serve_count)
+    rng = np.random.default_rng(12345)
+    arrive = np.cumsum(rng.exponential(1.0 / args.rate, len(reqs)))
+    items = [(r["graph"], vc.VC_MIN if r["kind"] == "min" else vc.VC_PARAM, r["k"])
+             for r in reqs]
+    solver = vc.Solver(0, node_limit=args.node_limit, watchdog_ms=120_000)
+    # warm up the server (first launch, buffers)
+    t = solver.submit(items[0][0], items[0][1], items[0][2])
+    solver.wait(t, items[0][0].n)
+    while True:  # until the warm-up launch is closed
+        try:
+            solver.mvc(gg.path(3), want_cover=False)
+            break
+        except vc.VCError as e:
+            if e.status != vc.VC_EAGAIN:
+                raise
+            time.sleep(0.002)
+    served = [None] * len(items)
+    pending = {}
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(items) or pending:
+        now = time.perf_counter() - t0
+        while i < len(items) and arrive[i] <= now:
+            g, kind, k = items[i]
+            pending[solver.submit(g, kind, k)] = i
+            i += 1
+        for tk in list(pending):
+            r = solver.poll(tk, items[pending[tk]][0].n)
+            if r is not None:
+                j = pending.pop(tk)
+                served[j] = (r[0], time.perf_counter() - t0)
+        time.sleep(0.0001)
+    lat = np.array([served[j][1] - arrive[j] for j in range(len(items))]) * 1e3
+    span = max(s[1] for s in served) - arrive[0]
+    # plain solver, FIFO at the same arrivals
+    while True:
+        try:
+            solver.mvc(gg.path(3), want_cover=False)
+            break
+        except vc.VCError as e:
+            if e.status != vc.VC_EAGAIN:
+                raise
+            time.sleep(0.002)
+    free_at, plat, agree = 0.0, [], 0
+    for j, (g, kind, k) in enumerate(items):
+        t1 = time.perf_counter()
+        if kind == vc.VC_MIN:
+            ans = solver.mvc(g, want_cover=True).size
+            same = ans == served[j][0]["size"]
+        else:
+            ans = solver.pvc(g, k, want_cover=True).yes
+            same = bool(ans) == bool(served[j][0]["yes"])
+        svc = time.perf_counter() - t1
+        start = max(arrive[j], free_at)
+        free_at = start + svc
+        plat.append((free_at - arrive[j]) * 1e3)
+        agree += int(same)
+    plat = np.array(plat)
+    solver.close()
+    return {
+        "metric": METRIC, "value": len(items) / span, "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": span * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+        "config": {"workload": f"served_stream_{len(items)}", "rate_per_s": args.rate,
+                   "p50_ms": float(np.percentile(lat, 50)),
+                   "p99_ms": float(np.percentile(lat, 99)),
+                   "plain_fifo_p50_ms": float(np.percentile(plat, 50)),
+                   "plain_fifo_p99_ms": float(np.percentile(plat, 99)),
+                   "plain_solves_per_s": len(items) / (free_at - arrive[0]),
+                   "same_answer_served_and_plain": f"{agree}/{len(items)}"},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["blocks_hubs", "batch", "serve"],
+                    default="blocks_hubs")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB device to "
+                         "device once: a kernel of known traffic that scales "
+                         "the HBM byte counters of a profiler run")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--node-limit", type=int, default=200_000)
+    ap.add_argument("--plain-count", type=int, default=256)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--serve-count", type=int, default=200)
+    ap.add_argument("--rate", type=float, default=100.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the search shards across GPUs only by instance, see the design notes",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_18334_amd import graphgen as gg
+    from paper_2512_18334_amd import vc
+
+    if not os.path.exists(vc.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    fn = {"blocks_hubs": bench_blocks_hubs, "batch": bench_batch, "serve": bench_serve}
+    out = fn[args.workload](args, torch, gg, vc)
     print(json.dumps(out), flush=True)
 
 

@@ -44,6 +44,17 @@ __device__ __forceinline__ uint32_t shfl(uint32_t x, uint32_t src) {
 __device__ __forceinline__ uint32_t op_add(uint32_t a, uint32_t b) { return a + b; }
 __device__ __forceinline__ uint32_t op_max(uint32_t a, uint32_t b) { return a > b ? a : b; }
 __device__ __forceinline__ uint32_t op_min(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint32_t op_or(uint32_t a, uint32_t b) { return a | b; }
+
+// bitwise OR of a 64-bit value over the 64 lanes (wave-uniform result)
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    VC_DPP_SCAN(lo, op_or, 0u);
+    VC_DPP_SCAN(hi, op_or, 0u);
+    // (readlane returns int: widen through uint32_t, never by sign extension)
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, 63) << 32) |
+           (uint64_t)(uint32_t)__builtin_amdgcn_readlane(lo, 63);
+}
 
 // inclusive prefix sum across the 64 lanes
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {

@@ -152,7 +152,8 @@ struct SearchArgs {
 
 // LDS layout of one worker: degree array, live list L, scratch lists Q and
 // R (R doubles as an id map of n_pad words), two bitmaps, 64 words of row
-// markers for the row expansion, graph cache.
+// markers for the row expansion and the small-node solver's masks and stack,
+// graph cache.
 struct LdsPlan {
     uint32_t L, Q, R, VB, PB, MK, G, bytes;
 };
@@ -166,7 +167,10 @@ inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd, uint32_t gcache_words) {
     uint32_t bw = (n_pad + 31u) / 32u;
     p.VB = at; at += 4u * bw;
     p.PB = at; at += 4u * bw;
-    p.MK = at; at += 4u * 64u;
+    at = (at + 15u) & ~15u;
+    // row markers (64 words), then the small-node solver's adjacency masks
+    // and stack (64 x u64 adjacency, 64 x (u64 live, u64 taken, u32 count))
+    p.MK = at; at += 4u * 64u + 8u * 64u * 3u + 4u * 64u;
     p.G = at; at += 4u * gcache_words;
     p.bytes = (at + 15u) & ~15u;
     return p;

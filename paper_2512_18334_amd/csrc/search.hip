@@ -107,6 +107,9 @@ struct Worker {
     uint64_t e2;    // sum of live degrees = 2|E|
     uint64_t key;   // max over live v of (deg << 32 | ~v): v_max, lowest id on ties
     bool known_connected;
+    bool small_off;  // this node goes through the general path (after a split)
+    uint64_t *ADJ, *SL, *SI;  // small-node solver: adjacency masks, stack
+    uint32_t* SS;
     // worker state
     uint8_t* stack;
     uint32_t bot, top;  // private stack as a deque: pop at top, donate from bot
@@ -133,6 +136,11 @@ struct Worker {
         VB = reinterpret_cast<uint32_t*>(lds + a.lds_VB);
         PB = reinterpret_cast<uint32_t*>(lds + a.lds_PB);
         MK = reinterpret_cast<uint32_t*>(lds + a.lds_MK);
+        ADJ = reinterpret_cast<uint64_t*>(lds + a.lds_MK + 256u);
+        SL = ADJ + 64;
+        SI = SL + 64;
+        SS = reinterpret_cast<uint32_t*>(SI + 64);
+        small_off = false;
         G = reinterpret_cast<uint32_t*>(lds + a.lds_G);
         stack = a.stacks + (size_t)blockIdx.x * a.stack_depth * a.slot_bytes;
         bot = top = 0;
@@ -619,6 +627,7 @@ struct Worker {
     __device__ __forceinline__ void begin_node(uint32_t bv) {
         build_live();
         known_connected = false;
+        small_off = false;
         if (bv != NONE) take_neighbours(bv);
     }
 
@@ -1343,6 +1352,273 @@ struct Worker {
         return CB_OK;
     }
 
+    // ------------------------------------------------------- small nodes
+
+    // A node with at most 64 live vertices is solved by the wave in
+    // registers: lane i holds live vertex L[i] (ids ascending, so lane order
+    // is id order) and its adjacency among them as a 64-bit mask; a node of
+    // the subtree is a pair of masks (live, taken) and the number taken.
+    // The same rules, stopping tests, component rules and branching vertex
+    // as for a general node apply to the whole subtree, depth first with a
+    // stack in LDS.  A split into two or more components that are not
+    // cliques or cycles returns to the general path, whose component branch
+    // goes through the registry (Alg. 2): the pending nodes of the subtree
+    // are pushed as ordinary nodes first.
+    enum { SMALL_DONE = 0, SMALL_STOP = 1, SMALL_SPLIT = 2 };
+
+    __device__ __forceinline__ static uint32_t popc64(uint64_t x) {
+        return (uint32_t)__builtin_popcountll(x);
+    }
+    __device__ __forceinline__ static uint32_t low64(uint64_t x) {
+        return (uint32_t)__builtin_ctzll(x);
+    }
+    __device__ __forceinline__ static uint32_t high64(uint64_t x) {
+        return 63u - (uint32_t)__builtin_clzll(x);
+    }
+
+    // the component of `seed` in `live` by breadth-first search on masks;
+    // odd: vertices at odd levels, last: the last level, depth: its level
+    __device__ __forceinline__ uint64_t small_bfs(uint64_t seed, uint64_t live, uint64_t adj,
+                                                  uint64_t& odd, uint64_t& last,
+                                                  uint32_t& depth) {
+        uint64_t vis = seed, fr = seed;
+        odd = 0;
+        last = seed;
+        depth = 0;
+        for (;;) {
+            const uint64_t nx = wave_or64(((fr >> lane()) & 1ull) ? adj : 0ull) & live & ~vis;
+            if (!nx) break;
+            ++depth;
+            if (depth & 1u) odd |= nx;
+            vis |= nx;
+            fr = nx;
+            last = nx;
+        }
+        return vis;
+    }
+
+    // Offer the small node's cover (entry marks plus the lanes in tin) as
+    // a new Best of the scope: the marks are put into the LDS degree array
+    // for the bitmap and taken out again.
+    __device__ __forceinline__ void small_improve(int val, uint64_t tin, bool mine, uint32_t vid,
+                                                  uint32_t d0) {
+        if (mine && ((tin >> lane()) & 1ull)) DG::set(deg, vid, DG::IN);
+        wave_sync();
+        improve(scope, val, -1);
+        if (mine) DG::set(deg, vid, d0);
+        wave_sync();
+        if (val < best) best = val;
+    }
+
+    // Push a small node (live, tin, taken count sv) as an ordinary node:
+    // its degree array is the entry one with the 64 lanes' entries replaced.
+    __device__ __forceinline__ bool small_export(uint64_t lv, uint64_t ti, int sv, bool mine,
+                                                 uint32_t vid, uint64_t adj) {
+        const uint32_t l = lane();
+        D* cd = reinterpret_cast<D*>(Q);
+        const uint64_t* s8 = reinterpret_cast<const uint64_t*>(deg);
+        uint64_t* d8 = reinterpret_cast<uint64_t*>(cd);
+        for (uint32_t i = l; i < (vpad * (uint32_t)sizeof(D)) / 8u; i += 64) d8[i] = s8[i];
+        wave_sync();
+        if (mine) {
+            const uint32_t x = ((lv >> l) & 1ull) ? popc64(adj & lv)
+                                                   : (((ti >> l) & 1ull) ? DG::IN : 0u);
+            DG::set(cd, vid, x);
+        }
+        wave_sync();
+        const uint32_t live = popc64(lv);
+        if (counted(scope) && lane() == 0) add_relaxed(&A.reg[scope].live, 1);
+        const int ss = sv, sc = scope;
+        return push_node(live, [&](uint8_t* slot, uint32_t stamp, bool coh) {
+            write_slot(slot, ss, sc, NONE, live, stamp, cd, view, vpad, coh);
+        });
+    }
+
+    __device__ __forceinline__ int small_solve() {
+        const uint32_t l = lane();
+        const uint32_t n0 = nl;
+        const bool mine = l < n0;
+        const uint32_t vid = mine ? L[l] : 0u;
+        const uint32_t d0 = mine ? DG::get(deg, vid) : 0u;
+        uint32_t* P = R + A.n_pad + 64u;  // view id -> lane
+        if (mine) P[vid] = l;
+        wave_sync();
+        uint64_t adj = 0;
+        if (mine) {
+            const uint32_t r1 = vo(vid + 1);
+            for (uint32_t e = vo(vid); e < r1; ++e) {
+                const uint32_t w = vc(e);
+                if (DG::live(DG::get(deg, w))) adj |= 1ull << P[w];
+            }
+        }
+        ADJ[l] = adj;
+        wave_sync();
+        const int s0 = s;
+        uint64_t live = n0 >= 64u ? ~0ull : ((1ull << n0) - 1ull);
+        uint64_t tin = 0;
+        int sl = 0;
+        int top = 0;
+        uint32_t since = 0;
+        bool first = true;
+        for (;;) {
+            if (!first) {
+                count_node();
+                // shared state (stop flags, the scope's Best) every 64 nodes
+                if ((++since & 63u) == 0u) {
+                    const int sr = stop_requested(true);
+                    if (sr == STOP_ALL) return SMALL_STOP;
+                    if (sr == DROP) return SMALL_DONE;
+                    const int cb = cur_best();
+                    if (cb < best) best = cb;
+                }
+            }
+            first = false;
+            bool dead = false;
+            uint32_t dg = 0;
+            // rules to a joint fixpoint, as for a general node
+            for (;;) {
+                const int b = best - s0 - sl - 1;
+                if (b < 0) {
+                    dead = true;
+                    break;
+                }
+                const bool lv = (live >> l) & 1ull;
+                const uint64_t nb = adj & live;
+                dg = lv ? popc64(nb) : 0u;
+                const uint64_t hi = ballot(lv && (int)dg > b);
+                if (hi) {
+                    tin |= hi;
+                    live &= ~hi;
+                    sl += (int)popc64(hi);
+                    continue;
+                }
+                const uint64_t d1 = ballot(lv && dg == 1u);
+                const uint64_t d2 = ballot(lv && dg == 2u);
+                bool fire = false;
+                if (lv && dg == 2u) {
+                    const uint32_t u = low64(nb), w = high64(nb);
+                    if ((ADJ[u] >> w) & 1ull)
+                        fire = !(((d2 >> u) & 1ull) && u < l) && !(((d2 >> w) & 1ull) && w < l);
+                }
+                const uint64_t F = ballot(fire);
+                // taken: a neighbour of a firing degree-two vertex, or the
+                // neighbour of a degree-one vertex (of two adjacent degree-one
+                // vertices, the higher id is taken)
+                bool take = false;
+                if (lv) {
+                    const uint64_t a1 = nb & d1;
+                    take = (nb & F) != 0ull ||
+                           (a1 != 0ull && (dg != 1u || (a1 & ((1ull << l) - 1ull)) != 0ull));
+                }
+                const uint64_t tk = ballot(take);
+                if (tk) {
+                    tin |= tk;
+                    live &= ~tk;
+                    sl += (int)popc64(tk);
+                    continue;
+                }
+                live &= ~ballot(lv && dg == 0u);  // no edges left: not live
+                break;
+            }
+            if (!dead) {
+                const int64_t b = (int64_t)best - s0 - sl - 1;
+                const uint64_t E = wave_sum(dg) / 2u;
+                if (b < 0 || (int64_t)E > b * b) {
+                    dead = true;
+                } else if (E == 0) {
+                    small_improve(s0 + sl, tin, mine, vid, d0);
+                    dead = true;
+                }
+            }
+            if (!dead && !(A.flags & VC_OPT_NO_COMPONENTS)) {
+                // components: cliques and chordless cycles are settled
+                uint64_t rest = live, keep = 0;
+                uint32_t nt = 0;
+                while (rest) {
+                    uint64_t odd, last;
+                    uint32_t depth;
+                    const uint64_t C = small_bfs(1ull << low64(rest), live, adj, odd, last, depth);
+                    rest &= ~C;
+                    const uint32_t size = popc64(C);
+                    const bool inC = (C >> l) & 1ull;
+                    const bool clique = ballot(inC && dg != size - 1u) == 0ull;
+                    const bool cyc = ballot(inC && dg != 2u) == 0ull;
+                    if (clique) {
+                        const uint64_t cov = C & ~(1ull << high64(C));
+                        tin |= cov;
+                        live &= ~C;
+                        sl += (int)size - 1;
+                    } else if (cyc) {
+                        uint64_t cov = odd;
+                        if ((size & 1u) && !(depth & 1u)) cov |= 1ull << low64(last);
+                        tin |= cov;
+                        live &= ~C;
+                        sl += (int)(size + 1u) / 2;
+                    } else {
+                        keep |= C;
+                        ++nt;
+                    }
+                }
+                if (s0 + sl >= best) {
+                    dead = true;
+                } else if (nt == 0) {
+                    small_improve(s0 + sl, tin, mine, vid, d0);
+                    dead = true;
+                } else if (nt >= 2) {
+                    // split: the pending nodes go out as ordinary nodes, this
+                    // node continues on the general path
+                    while (top > 0) {
+                        --top;
+                        if (!small_export(SL[top], SI[top], s0 + (int)SS[top], mine, vid, adj))
+                            return SMALL_STOP;
+                    }
+                    if (mine) {
+                        const uint32_t x = ((live >> l) & 1ull)
+                                               ? popc64(adj & live)
+                                               : (((tin >> l) & 1ull) ? DG::IN : 0u);
+                        DG::set(deg, vid, x);
+                    }
+                    wave_sync();
+                    s = s0 + sl;
+                    recompact();
+                    return SMALL_SPLIT;
+                }
+                // one component left: its degrees are unchanged, so the rules
+                // have nothing new and it is branched on
+            }
+            if (!dead) {
+                // branch on the highest degree (lowest id on ties): the
+                // N(v) child is pushed, the v child continues
+                const bool lv = (live >> l) & 1ull;
+                const uint32_t key = wave_max(lv ? (dg << 6) | (63u - l) : 0u);
+                const uint32_t v = 63u - (key & 63u);
+                const uint64_t nbv = ADJ[v] & live;
+                if (top >= 64) {
+                    // cannot happen: every pending entry took a vertex out of
+                    // the path's live set
+                    fail(VC_EDEVICE);
+                    return SMALL_STOP;
+                }
+                if (lane() == 0) {
+                    SL[top] = live & ~(nbv | (1ull << v));
+                    SI[top] = tin | nbv;
+                    SS[top] = (uint32_t)(sl + (int)popc64(nbv));
+                }
+                wave_sync();
+                ++top;
+                live &= ~(1ull << v);
+                tin |= 1ull << v;
+                sl += 1;
+                continue;
+            }
+            if (top == 0) return SMALL_DONE;
+            --top;
+            live = SL[top];
+            tin = SI[top];
+            sl = (int)SS[top];
+        }
+    }
+
     // Process one node and, depth-first, its first children in place.
     // Returns true when the whole search stops.
     __device__ __forceinline__ bool process(bool check_now) {
@@ -1379,6 +1655,21 @@ struct Worker {
                 charge(CYC_COMPLETE);
                 return false;
             }
+            if (nl <= 64u && !small_off) {
+                const int r = small_solve();
+                charge(CYC_REDUCE);
+                if (r == SMALL_STOP) return true;
+                if (r == SMALL_DONE) {
+                    complete(scope);
+                    charge(CYC_COMPLETE);
+                    return false;
+                }
+                // split into components: on to the component branch
+                small_off = true;
+                known_connected = false;
+                recount = false;
+                continue;
+            }
             if (!(A.flags & VC_OPT_NO_COMPONENTS) && !known_connected) {
                 const uint32_t nc = find_components();
                 const uint32_t nt = settle_simple_components(nc);
@@ -1404,7 +1695,10 @@ struct Worker {
                 } else {
                     const int cb = component_branch(nc, nt);
                     charge(CYC_COMPONENTS);
-                    if (cb == CB_OK) continue;
+                    if (cb == CB_OK) {
+                        small_off = false;
+                        continue;
+                    }
                     if (cb == CB_PRUNED) {
                         complete(scope);
                         charge(CYC_COMPLETE);
@@ -1423,6 +1717,7 @@ struct Worker {
             const bool ok = vertex_branch();
             charge(CYC_BRANCH);
             if (!ok) return false;
+            small_off = false;
         }
     }
 
