@@ -39,7 +39,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_blocks_hubs_traffic.json")
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("search.hip", "dev_common.hpp", "internal.hpp"):
+    for f in ("search_worker.hpp", "search_deg.hip", "search.hip", "dev_common.hpp",
+              "internal.hpp"):
         with open(os.path.join(ROOT, "paper_2512_18334_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -71,6 +71,7 @@ typedef struct {
 #define VC_OPT_VALIDATE_SKIP 4u /* trust the caller: skip the CSR checks     */
 #define VC_OPT_NO_GRAPH 8u      /* batches: launch the kernels one by one
                                    instead of replaying a captured hipGraph */
+#define VC_OPT_NO_SMALL 16u     /* no register-resident small-node solver   */
 
 /*
  * Tuning knobs.  Zero in any field selects the library default.
@@ -99,6 +100,12 @@ typedef struct {
  *   serve_slots   serving: instance slots of one resident launch (default
  *                 4096); when they or its graph arena run out, the resident
  *                 kernel drains and is launched again.
+ *   small_max     nodes with at most this many live vertices are solved in
+ *                 registers (bit masks, one wave; at most 128).  Default: 64
+ *                 for vc_min / vc_param (one tree must split over the
+ *                 workers), 128 for batches and served requests (many
+ *                 instances keep the workers busy).  VC_OPT_NO_SMALL turns
+ *                 it off.
  *   gcache_words  LDS graph cache per worker, in 32-bit words: components
  *                 whose induced subgraph fits are re-induced with local ids
  *                 (default: the most that still fits three workers per CU).
@@ -116,6 +123,7 @@ typedef struct {
     uint32_t gcache_words;
     uint32_t serve_n_max;
     uint32_t serve_slots;
+    uint32_t small_max;
 } vc_opts;
 
 /* Statistics of the last completed solve on a context. */

@@ -1,6 +1,7 @@
 """Compile libvc.so (HIP, gfx950) in-tree with hipcc.
 
-Each .hip source under csrc/ is compiled to an object in parallel, then
+Each .hip source under csrc/ is compiled to an object in parallel (the
+search worker once per degree-array type), then
 linked into paper_2512_18334_amd/libvc.so.  Always recompiles.
 """
 from __future__ import annotations
@@ -16,7 +17,13 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvc.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "batch.hip", "root.hip", "search.hip", "serve.hip"]
+# (source, object name, extra flags); the search worker is built once per
+# degree-array type so the three instantiations compile in parallel
+SOURCES = [("api.hip", "api", []), ("batch.hip", "batch", []), ("root.hip", "root", []),
+           ("search.hip", "search", []), ("serve.hip", "serve", []),
+           ("search_deg.hip", "search_d1", ["-DVC_DEG_BYTES=1"]),
+           ("search_deg.hip", "search_d2", ["-DVC_DEG_BYTES=2"]),
+           ("search_deg.hip", "search_d4", ["-DVC_DEG_BYTES=4"])]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -34,9 +41,10 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libvc)")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(entry) -> str:
+    src, name, extra = entry
+    obj = os.path.join(BUILD_DIR, name + ".o")
+    cmd = [_hipcc(), *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

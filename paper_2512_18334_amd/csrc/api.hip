@@ -365,6 +365,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         a.k = pvc ? (int)k - (int)sroot : 0;
         a.flags = c->opts.flags;
         a.donate_slack = c->opts.donate_slack;
+        // one search: 64 (the tree must split over the workers; subtrees
+        // below 64 live vertices stay short)
+        a.small_max = (c->opts.flags & VC_OPT_NO_SMALL) ? 0u
+                      : std::min<uint32_t>(c->opts.small_max ? c->opts.small_max : 64u, 128u);
         a.node_limit = c->opts.node_limit;
         a.n_roots = 1;  // one root scope (entry 0); no instance claims
         a.batch = 0;

@@ -326,6 +326,9 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     a.k = 0;
     a.flags = c->opts.flags;
     a.donate_slack = c->opts.donate_slack;
+    // many instances keep the workers busy: up to 128 live vertices
+    a.small_max = (c->opts.flags & VC_OPT_NO_SMALL) ? 0u
+                  : std::min<uint32_t>(c->opts.small_max ? c->opts.small_max : 128u, 128u);
     a.donate_min = c->opts.donate_min ? c->opts.donate_min : 48u;
     a.strong_fences = 0;
     a.node_limit = 0;

@@ -148,6 +148,7 @@ struct SearchArgs {
     // instance i like a PVC answer does.
     uint32_t serve;
     const int* inst_cancel;
+    uint32_t small_max;  // live vertices up to which a node is solved in registers (0: never)
 };
 
 // LDS layout of one worker: degree array, live list L, scratch lists Q and
@@ -169,8 +170,9 @@ inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd, uint32_t gcache_words) {
     p.PB = at; at += 4u * bw;
     at = (at + 15u) & ~15u;
     // row markers (64 words), then the small-node solver's adjacency masks
-    // and stack (64 x u64 adjacency, 64 x (u64 live, u64 taken, u32 count))
-    p.MK = at; at += 4u * 64u + 8u * 64u * 3u + 4u * 64u;
+    // and stack: 128 x 2 u64 adjacency, 128 x (2 u64 live, 2 u64 taken),
+    // 128 u32 counts
+    p.MK = at; at += 4u * 64u + 8u * 128u * 2u + 8u * 128u * 4u + 4u * 128u;
     p.G = at; at += 4u * gcache_words;
     p.bytes = (at + 15u) & ~15u;
     return p;

@@ -190,6 +190,9 @@ vc_status Server::plan() {
     a.pvc = 0;
     a.flags = c->opts.flags;
     a.donate_slack = c->opts.donate_slack;
+    // many instances keep the workers busy: up to 128 live vertices
+    a.small_max = (c->opts.flags & VC_OPT_NO_SMALL) ? 0u
+                  : std::min<uint32_t>(c->opts.small_max ? c->opts.small_max : 128u, 128u);
     a.donate_min = c->opts.donate_min ? c->opts.donate_min : 48u;
     a.watchdog_ticks =
         (uint64_t)c->wall_khz * (c->opts.watchdog_ms ? c->opts.watchdog_ms : 120000u);

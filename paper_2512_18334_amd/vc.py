@@ -24,6 +24,7 @@ VC_OPT_NO_COMPONENTS = 1
 VC_OPT_NO_LOAD_BALANCE = 2
 VC_OPT_VALIDATE_SKIP = 4
 VC_OPT_NO_GRAPH = 8
+VC_OPT_NO_SMALL = 16
 VC_MIN, VC_PARAM = 0, 1
 
 CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]
@@ -53,7 +54,8 @@ class vc_opts(ctypes.Structure):
                 ("hbm_budget", ctypes.c_uint64), ("node_limit", ctypes.c_uint64),
                 ("flags", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
                 ("donate_min", ctypes.c_uint32), ("gcache_words", ctypes.c_uint32),
-                ("serve_n_max", ctypes.c_uint32), ("serve_slots", ctypes.c_uint32)]
+                ("serve_n_max", ctypes.c_uint32), ("serve_slots", ctypes.c_uint32),
+                ("small_max", ctypes.c_uint32)]
 
 
 class vc_result(ctypes.Structure):
@@ -265,11 +267,12 @@ class Solver:
                  registry_cap: int = 0, hbm_budget: int = 0,
                  node_limit: int = 0, flags: int = 0, watchdog_ms: int = 0,
                  donate_min: int = 0, gcache_words: int = 0, serve_n_max: int = 0,
-                 serve_slots: int = 0):
+                 serve_slots: int = 0, small_max: int = 0):
         lib = load()
         self._opts = vc_opts(workers, donate_slack, worklist_cap, registry_cap,
                              hbm_budget, node_limit, flags, watchdog_ms,
-                             donate_min, gcache_words, serve_n_max, serve_slots)
+                             donate_min, gcache_words, serve_n_max, serve_slots,
+                             small_max)
         h = ctypes.c_void_p()
         st = lib.vc_ctx_create(int(device), stream, ctypes.byref(self._opts),
                                ctypes.byref(h))

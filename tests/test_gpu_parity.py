@@ -163,6 +163,8 @@ def test_ablation_switches_agree(solver, orc, libvc):
     exp_hubs = orc.mvc(hubs)["size"]
     for kw in [dict(flags=vc.VC_OPT_NO_COMPONENTS),
                dict(flags=vc.VC_OPT_NO_LOAD_BALANCE),
+               dict(flags=vc.VC_OPT_NO_SMALL), dict(small_max=64),
+               dict(flags=vc.VC_OPT_NO_COMPONENTS | vc.VC_OPT_NO_SMALL),
                dict(workers=1), dict(workers=3),
                dict(registry_cap=64), dict(worklist_cap=8)]:
         with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000, **kw) as s2:
