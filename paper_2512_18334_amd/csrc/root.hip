@@ -34,6 +34,12 @@ __device__ __forceinline__ void wave_atomic_add(uint32_t* p, uint32_t x) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (n);          \
          i += gridDim.x * blockDim.x)
 
+// one wave per vertex (its lanes stride the row), so a hub's row costs one
+// pass instead of one thread walking it alone
+#define WAVE_LOOP(v, n)                                                        \
+    for (uint32_t v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < (n);   \
+         v += (gridDim.x * blockDim.x) >> 6)
+
 // ------------------------------------------------------------- validation
 
 // offsets: off[0] == 0, non-decreasing, off[n] == nnz
@@ -104,17 +110,42 @@ __global__ void k_init(uint32_t n, const uint32_t* off, uint32_t* rdeg, uint32_t
 template <typename C>
 __global__ void k_greedy_select(uint32_t n, const uint32_t* off, const C* col,
                                 const uint32_t* gdeg, uint8_t* sel, uint32_t* ctr_live) {
+    // 64 consecutive vertices per wave, one per lane; a row longer than 32
+    // entries is walked by the whole wave together (hubs take one pass)
+    const uint32_t l = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
     uint32_t live = 0;
-    GRID_LOOP(v, n) {
-        const uint32_t d = gdeg[v];
-        if (d == 0) continue;
-        ++live;
+    for (uint32_t base = wave * 64u; base < n; base += waves * 64u) {
+        const uint32_t v = base + l;
+        const uint32_t d = v < n ? gdeg[v] : 0u;
+        const uint32_t r0 = v < n ? off[v] : 0u, r1 = v < n ? off[v + 1] : 0u;
         const uint64_t kv = ((uint64_t)d << 32) | (uint32_t)~v;
-        bool top = true;
-        for (uint32_t e = off[v]; e < off[v + 1] && top; ++e) {
-            uint32_t u = (uint32_t)col[e];
-            uint32_t du = gdeg[u];
-            if (du && (((uint64_t)du << 32) | (uint32_t)~u) > kv) top = false;
+        const bool longrow = d != 0u && r1 - r0 > 32u;
+        bool top = d != 0u;
+        if (d != 0u) ++live;
+        if (d != 0u && !longrow) {
+            for (uint32_t e = r0; e < r1 && top; ++e) {
+                const uint32_t u = (uint32_t)col[e];
+                const uint32_t du = gdeg[u];
+                if (du && (((uint64_t)du << 32) | (uint32_t)~u) > kv) top = false;
+            }
+        }
+        uint64_t m = ballot(longrow);
+        while (m) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1ull;
+            const uint32_t a = shfl(r0, j), b = shfl(r1, j);
+            const uint32_t vj = shfl(v, j), dj = shfl(d, j);
+            const uint64_t kj = ((uint64_t)dj << 32) | (uint32_t)~vj;
+            bool beaten = false;
+            for (uint32_t e = a + l; e < b; e += 64) {
+                const uint32_t u = (uint32_t)col[e];
+                const uint32_t du = gdeg[u];
+                if (du && (((uint64_t)du << 32) | (uint32_t)~u) > kj) beaten = true;
+            }
+            const bool any = ballot(beaten) != 0ull;
+            if (l == j) top = !any;
         }
         if (top) sel[v] = 1;
     }
@@ -126,17 +157,23 @@ __global__ void k_greedy_apply(uint32_t n, const uint32_t* off, const C* col, ui
                                uint8_t* sel, uint8_t* gin, const uint32_t* ctr_live,
                                uint32_t* ctr_size) {
     if (*ctr_live == 0) return;
+    const uint32_t l = threadIdx.x & 63u;
     uint32_t taken = 0;
-    GRID_LOOP(v, n) {
+    WAVE_LOOP(v, n) {
         if (!sel[v]) continue;
-        sel[v] = 0;
-        gin[v] = 1;
-        ++taken;
-        for (uint32_t e = off[v]; e < off[v + 1]; ++e) {
-            uint32_t u = (uint32_t)col[e];
+        // selected vertices are never adjacent (strict local maxima), so
+        // every neighbour still has the edge to v: no underflow
+        const uint32_t r1 = off[v + 1];
+        for (uint32_t e = off[v] + l; e < r1; e += 64) {
+            const uint32_t u = (uint32_t)col[e];
             if (gdeg[u]) atomicSub(&gdeg[u], 1u);
         }
-        gdeg[v] = 0;
+        if (l == 0) {
+            sel[v] = 0;
+            gin[v] = 1;
+            gdeg[v] = 0;
+            ++taken;
+        }
     }
     wave_atomic_add(ctr_size, taken);
 }
@@ -218,13 +255,15 @@ __global__ void k_reduce_mark(uint32_t n, uint32_t* rdeg, uint8_t* addf, uint8_t
 template <typename C>
 __global__ void k_reduce_remove(uint32_t n, const uint32_t* off, const C* col, uint32_t* rdeg,
                                 uint8_t* newly) {
-    GRID_LOOP(v, n) {
+    const uint32_t l = threadIdx.x & 63u;
+    WAVE_LOOP(v, n) {
         if (!newly[v]) continue;
-        newly[v] = 0;
-        for (uint32_t e = off[v]; e < off[v + 1]; ++e) {
-            uint32_t u = (uint32_t)col[e];
+        const uint32_t r1 = off[v + 1];
+        for (uint32_t e = off[v] + l; e < r1; e += 64) {
+            const uint32_t u = (uint32_t)col[e];
             if (rlive(rdeg[u])) atomicSub(&rdeg[u], 1u);
         }
+        if (l == 0) newly[v] = 0;
     }
 }
 
@@ -366,6 +405,14 @@ static inline uint32_t grid_for(uint64_t n, uint32_t t = 256) {
     return (uint32_t)b;
 }
 
+// blocks of 256 threads for one wave per vertex
+static inline uint32_t grid_for_waves(uint64_t n) {
+    uint64_t b = (n + 3) / 4;
+    if (b < 1) b = 1;
+    if (b > 16384) b = 16384;
+    return (uint32_t)b;
+}
+
 hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* hsum,
                          hipStream_t st, uint32_t* bad_host) {
     hipError_t e;
@@ -406,14 +453,14 @@ static hipError_t greedy_t(const RootGraph& g, const RootBufs& b, hipStream_t st
                            uint32_t* rounds) {
     const C* col = (const C*)g.col;
     hipError_t e;
-    const uint32_t grid = grid_for(g.n);
+    const uint32_t wgrid = grid_for_waves(g.n);
     for (uint32_t r = 0;; r += 4) {
         for (uint32_t j = 0; j < 4; ++j) {
             uint32_t* live = b.ctr + CTR_GLIVE + ((r + j) & 1u);
             if ((e = hipMemsetAsync(live, 0, 4, st))) return e;
-            hipLaunchKernelGGL(k_greedy_select<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
+            hipLaunchKernelGGL(k_greedy_select<C>, dim3(wgrid), dim3(256), 0, st, g.n, g.off, col,
                                b.gdeg, b.addf, live);
-            hipLaunchKernelGGL(k_greedy_apply<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
+            hipLaunchKernelGGL(k_greedy_apply<C>, dim3(wgrid), dim3(256), 0, st, g.n, g.off, col,
                                b.gdeg, b.addf, b.gin, live, b.ctr + CTR_GSIZE);
         }
         if ((e = hipGetLastError())) return e;
@@ -447,8 +494,8 @@ static hipError_t reduce_t(const RootGraph& g, const RootBufs& b, int best0, hip
                                b.rdeg, b.addf, b.ctr, r, best0);
             hipLaunchKernelGGL(k_reduce_mark, dim3(grid), dim3(256), 0, st, g.n, b.rdeg, b.addf,
                                b.newly, b.ctr, r);
-            hipLaunchKernelGGL(k_reduce_remove<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
-                               b.rdeg, b.newly);
+            hipLaunchKernelGGL(k_reduce_remove<C>, dim3(grid_for_waves(g.n)), dim3(256), 0, st,
+                               g.n, g.off, col, b.rdeg, b.newly);
         }
         if ((e = hipGetLastError())) return e;
         uint32_t fired = 0;

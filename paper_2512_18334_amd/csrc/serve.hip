@@ -342,14 +342,17 @@ vc_status Server::start(Req& r) {
     r.res.kind = r.kind;
     r.res.n = r.n;
     vc_csr g{r.n, r.nnz, r.off.data(), r.nnz ? (const void*)r.col.data() : nullptr, r.col_bytes, 0};
-    if (!(c->opts.flags & VC_OPT_VALIDATE_SKIP)) {
-        vc_status vs = validate_host(&g);
-        if (vs) {
-            r.res.status = vs;
-            return VC_OK;
-        }
-    }
+    const bool check = !(c->opts.flags & VC_OPT_VALIDATE_SKIP);
     if (r.n == 0 || r.nnz == 0) {
+        // nothing to search; the offsets must still be all zero
+        if (check) {
+            bool ok = r.off[0] == 0u;
+            for (uint32_t v = 0; ok && v < r.n; ++v) ok = r.off[v + 1] == 0u;
+            if (!ok || r.nnz) {
+                r.res.status = VC_EINVAL;
+                return VC_OK;
+            }
+        }
         r.res.status = VC_OK;
         r.res.size = 0;
         r.res.yes = 1;
@@ -365,7 +368,20 @@ vc_status Server::start(Req& r) {
     HIPCHK(hipMemcpyAsync(in_col.p, r.col.data(), (size_t)r.col_bytes * r.nnz,
                           hipMemcpyHostToDevice, ss));
     hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, b.ctr, (uint64_t)CTR_COUNT);
+    hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, (uint32_t*)b.hsum, (uint64_t)2);
     HIPCHK(hipGetLastError());
+    if (check) {
+        // the checks vc_validate applies to a device graph (kernels; the
+        // symmetry test by a 64-bit hash of the unordered pairs)
+        uint32_t bad = 0;
+        HIPCHK(root_validate(rg, b.ctr, b.hsum, ss, &bad));
+        if (bad) {
+            r.res.status = VC_EINVAL;
+            return VC_OK;
+        }
+        hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, b.ctr, (uint64_t)CTR_COUNT);
+        HIPCHK(hipGetLastError());
+    }
     HIPCHK(root_init(rg, b, ss));
     uint32_t grounds = 0;
     HIPCHK(root_greedy(rg, b, ss, &grounds));

@@ -118,3 +118,15 @@ def test_device_graph_submission(solver, orc):
     e = orc.mvc(g)["size"]
     assert res["size"] == e
     assert_cover(g, cov, size=e)
+
+
+def test_invalid_request_is_answered_with_einval(solver):
+    good = gg.petersen()
+    bad = gg.Graph(good.n, good.offsets.copy(), good.cols.copy())
+    bad.cols[0] = 0  # self-loop
+    t_bad = solver.submit(bad)
+    t_good = solver.submit(good)
+    res, cov = solver.wait(t_bad, bad.n)
+    assert res["status"] == vc.VC_EINVAL and cov.size == 0
+    res, cov = solver.wait(t_good, good.n)
+    assert res["status"] == vc.VC_OK and res["size"] == 6
