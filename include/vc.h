@@ -72,6 +72,15 @@ typedef struct {
 #define VC_OPT_NO_GRAPH 8u      /* batches: launch the kernels one by one
                                    instead of replaying a captured hipGraph */
 #define VC_OPT_NO_SMALL 16u     /* no register-resident small-node solver   */
+#define VC_OPT_NO_INDUCE 32u    /* single solves: no root reduction and no
+                                   induced subgraph; the search starts from
+                                   the input graph in its own ids (Sec. IV-B
+                                   off, Table II)                           */
+#define VC_OPT_NO_COMPACT 64u   /* rebuild the live list by a sweep of the
+                                   whole degree array after every rule pass
+                                   instead of filtering the previous list
+                                   (bounding of non-zero entries off,
+                                   Table II)                                */
 
 /*
  * Tuning knobs.  Zero in any field selects the library default.

@@ -256,8 +256,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     }
 
     // root reduction to a fixpoint under the bound best0 (Sec. IV-B)
+    // (skipped under VC_OPT_NO_INDUCE: the search starts from the input)
+    const bool no_induce = (c->opts.flags & VC_OPT_NO_INDUCE) != 0;
     uint32_t rounds = 0;
-    HIPCHK(root_reduce(rg, b, best0, s, 1u << 16, &rounds));
+    if (!no_induce) HIPCHK(root_reduce(rg, b, best0, s, 1u << 16, &rounds));
     stv.root_rounds = rounds;
     uint32_t sroot = 0;
     HIPCHK(hipMemcpyAsync(&sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
@@ -270,7 +272,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     }
 
     // induce the subgraph on the vertices that still have edges
-    HIPCHK(root_induce_a(rg, b, s));
+    HIPCHK(root_induce_a(rg, b, s, no_induce));
     uint32_t hdr[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(&hdr[0], b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, s));

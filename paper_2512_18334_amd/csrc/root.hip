@@ -338,16 +338,19 @@ __global__ void k_scan_apply(const T* in, uint32_t N, const uint32_t* sums, uint
 
 // ------------------------------------------------------------- induce
 
-__global__ void k_live_flags(uint32_t n, const uint32_t* rdeg, uint32_t* flag) {
-    GRID_LOOP(v, n) flag[v] = rlive(rdeg[v]) ? 1u : 0u;
+__global__ void k_live_flags(uint32_t n, const uint32_t* rdeg, uint32_t* flag, int keep_all) {
+    GRID_LOOP(v, n) flag[v] = (keep_all || rlive(rdeg[v])) ? 1u : 0u;
 }
 
 __global__ void k_induce_deg(uint32_t n, const uint32_t* rdeg, const uint32_t* newid,
-                             uint32_t* kdeg, uint32_t* oldid, uint32_t* ctr) {
+                             uint32_t* kdeg, uint32_t* oldid, uint32_t* ctr, int keep_all) {
     uint32_t mx = 0;
     GRID_LOOP(v, n) {
-        const uint32_t d = rdeg[v];
-        if (!rlive(d)) continue;
+        uint32_t d = rdeg[v];
+        if (!rlive(d)) {
+            if (!keep_all) continue;
+            d = 0;
+        }
         const uint32_t i = newid[v];
         kdeg[i] = d;
         oldid[i] = v;
@@ -524,12 +527,13 @@ hipError_t scan_u32(const uint32_t* in, uint32_t N, uint32_t* out, uint32_t* tmp
     return hipGetLastError();
 }
 
-hipError_t root_induce_a(const RootGraph& g, const RootBufs& b, hipStream_t st) {
-    hipLaunchKernelGGL(k_live_flags, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, b.rdeg, b.flags);
+hipError_t root_induce_a(const RootGraph& g, const RootBufs& b, hipStream_t st, bool keep_all) {
+    hipLaunchKernelGGL(k_live_flags, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, b.rdeg, b.flags,
+                       (int)keep_all);
     hipError_t e = scan_u32(b.flags, g.n, b.newid, b.scan_tmp, st);
     if (e) return e;
     hipLaunchKernelGGL(k_induce_deg, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, b.rdeg, b.newid,
-                       b.kdeg, b.oldid, b.ctr);
+                       b.kdeg, b.oldid, b.ctr, (int)keep_all);
     return hipGetLastError();
 }
 

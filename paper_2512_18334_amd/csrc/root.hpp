@@ -50,7 +50,9 @@ hipError_t root_init(const RootGraph& g, const RootBufs& b, hipStream_t st);
 hipError_t root_greedy(const RootGraph& g, const RootBufs& b, hipStream_t st, uint32_t* rounds);
 hipError_t root_reduce(const RootGraph& g, const RootBufs& b, int best0, hipStream_t st,
                        uint32_t max_rounds, uint32_t* rounds);
-hipError_t root_induce_a(const RootGraph& g, const RootBufs& b, hipStream_t st);
+// keep_all: every input vertex keeps its id (isolated ones with degree 0)
+hipError_t root_induce_a(const RootGraph& g, const RootBufs& b, hipStream_t st,
+                         bool keep_all = false);
 hipError_t root_induce_b(const RootGraph& g, const RootBufs& b, uint32_t np, uint32_t kcol_bytes,
                          hipStream_t st);
 hipError_t root_cover(const RootGraph& g, const RootBufs& b, uint32_t np, int improved,

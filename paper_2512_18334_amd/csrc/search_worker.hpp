@@ -301,6 +301,10 @@ struct Worker {
 
     // drop the vertices of L that are no longer live (order kept)
     __device__ __forceinline__ void recompact() {
+        if (A.flags & VC_OPT_NO_COMPACT) {
+            build_live();  // ablation: a sweep of the whole degree array
+            return;
+        }
         const uint32_t l = lane();
         uint32_t cnt = 0;
         for (uint32_t base = 0; base < nl; base += 64) {

@@ -25,6 +25,8 @@ VC_OPT_NO_LOAD_BALANCE = 2
 VC_OPT_VALIDATE_SKIP = 4
 VC_OPT_NO_GRAPH = 8
 VC_OPT_NO_SMALL = 16
+VC_OPT_NO_INDUCE = 32
+VC_OPT_NO_COMPACT = 64
 VC_MIN, VC_PARAM = 0, 1
 
 CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]

@@ -152,3 +152,14 @@ def test_serving_entry_points_reject_missing_context(libvc):
     r = vc.vc_result()
     assert libvc.vc_poll(None, 1, ctypes.byref(r), None) == vc.VC_EINVAL
     assert libvc.vc_cancel(None, 1) == vc.VC_EINVAL
+
+
+def test_python_constants_match_the_header():
+    """Every #define and vc_status value in include/vc.h has the same value in
+    the Python binding."""
+    text = open(HEADER).read()
+    found = dict(re.findall(r"^#define (VC_[A-Z_]+) (\d+)u?\b", text, re.M))
+    found.update(re.findall(r"^\s+(VC_[A-Z]+) = (-?\d+),", text, re.M))
+    assert {"VC_OPT_NO_INDUCE", "VC_OPT_NO_COMPACT", "VC_EINVAL", "VC_MIN"} <= set(found)
+    for name, val in found.items():
+        assert getattr(vc, name) == int(val), name

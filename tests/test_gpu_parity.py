@@ -165,6 +165,8 @@ def test_ablation_switches_agree(solver, orc, libvc):
                dict(flags=vc.VC_OPT_NO_LOAD_BALANCE),
                dict(flags=vc.VC_OPT_NO_SMALL), dict(small_max=64),
                dict(flags=vc.VC_OPT_NO_COMPONENTS | vc.VC_OPT_NO_SMALL),
+               dict(flags=vc.VC_OPT_NO_INDUCE), dict(flags=vc.VC_OPT_NO_COMPACT),
+               dict(flags=vc.VC_OPT_NO_INDUCE | vc.VC_OPT_NO_COMPACT | vc.VC_OPT_NO_SMALL),
                dict(workers=1), dict(workers=3),
                dict(registry_cap=64), dict(worklist_cap=8)]:
         with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000, **kw) as s2:
@@ -172,6 +174,35 @@ def test_ablation_switches_agree(solver, orc, libvc):
                 gpu_mvc(s2, g, e)
             if not kw.get("flags", 0) & vc.VC_OPT_NO_COMPONENTS:
                 gpu_mvc(s2, hubs, exp_hubs)
+
+
+def test_no_induce_searches_the_input_graph(orc, libvc):
+    """With the root reduction and induction off the search starts from the
+    input in its own ids: nothing is forced at the root, every vertex
+    (isolated ones included) keeps its id, and answers are unchanged."""
+    g0 = gg.config2_blocks_hubs(seed=31, nblocks=4, bsize=24, nhubs=2, per_block=6)
+    # pendant paths (the degree-one rule fires at the root) and 5 isolated vertices
+    extra = 5
+    us, vs = [], []
+    for i in range(8):
+        a = g0.n + extra + 2 * i
+        us += [i * 3, a]
+        vs += [a, a + 1]
+    src = np.repeat(np.arange(g0.n), np.diff(g0.offsets.astype(np.int64)))
+    keep = src < g0.cols
+    eu, ev = src[keep], g0.cols[keep].astype(np.int64)
+    g = gg.from_edges(g0.n + extra + 16, np.concatenate([eu, us]), np.concatenate([ev, vs]))
+    e = orc.mvc(g)["size"]
+    with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000) as s0:
+        r0 = gpu_mvc(s0, g, e)
+    assert r0.stats["forced_root"] > 0
+    for flags in (vc.VC_OPT_NO_INDUCE, vc.VC_OPT_NO_INDUCE | vc.VC_OPT_NO_COMPACT):
+        with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000, flags=flags) as s:
+            r = gpu_mvc(s, g, e)
+            assert r.stats["forced_root"] == 0 and r.stats["root_rounds"] == 0
+            assert r.stats["n_kernel"] == g.n
+            for k in (e - 1, e):
+                assert s.pvc(g, k).yes == (e <= k)
 
 
 def _hub_graph(hub_degree, seed):
