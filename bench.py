@@ -89,6 +89,18 @@ def roofline(stats_list, search_ms):
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(alg_bytes)}
 
 
+def cycle_breakdown(stats):
+    """Share of the search workers' shader cycles per activity (Fig. 4):
+    fetching nodes, reduction rules, component detection and branching,
+    vertex branching, registry completion, idle."""
+    tot = {}
+    for s in stats:
+        for k, v in s["cycles"].items():
+            tot[k] = tot.get(k, 0) + v
+    all_ = sum(tot.values()) or 1
+    return {k: round(100.0 * v / all_, 2) for k, v in tot.items()}
+
+
 def bench_blocks_hubs(args, torch, gg, vc):
     g = gg.config2_blocks_hubs()
     dg = vc.DeviceGraph.from_graph(g, "cuda:0")
@@ -130,7 +142,8 @@ def bench_blocks_hubs(args, torch, gg, vc):
                    "search_kernel_ms": search_ms, "workers": s0["workers"],
                    "deg_bytes": s0["deg_bytes"],
                    "component_branches_per_solve":
-                       sum(s["component_branches"] for s in stats) / len(stats)},
+                       sum(s["component_branches"] for s in stats) / len(stats),
+                   "cycle_breakdown_pct": cycle_breakdown(stats)},
         "roofline": roofline(stats, search_ms),
     }
     if args.copy_mib:

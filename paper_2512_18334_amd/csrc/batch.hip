@@ -37,67 +37,101 @@ __device__ __forceinline__ uint64_t pair_hash(uint32_t a, uint32_t b) {
 }
 
 // Device-side check of a packed batch.  bad[i] bits: 1 offsets, 2 range or
-// self-loop, 4 repeated entry, 8 long unsorted row left unchecked (not an
-// error); hs[i] the symmetry hash sum; *maxdeg the largest row.
+// self-loop, 4 repeated entry; hs[i] the symmetry hash sum; *maxdeg the
+// largest row.  64 consecutive rows of the packed batch per wave, one per
+// lane; a row longer than 32 entries is checked by the whole wave.
 __global__ void __launch_bounds__(256) k_batch_check(
     uint32_t count, const uint64_t* rbase, const uint32_t* n, const uint64_t* nnz,
     const uint64_t* offs_base, const uint64_t* cols_base, const uint32_t* offsets,
     const void* cols, uint32_t col_bytes, uint32_t* bad, unsigned long long* hs,
     uint32_t* maxdeg) {
     __shared__ uint32_t red[256];
+    __shared__ uint32_t tbl_all[4 * ROWCHK_TBL];
+    uint32_t* tbl = tbl_all + (threadIdx.x >> 6) * ROWCHK_TBL;
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = gid; i < count; i += stride) {
         const uint32_t* off = offsets + offs_base[i];
         if (off[0] != 0u || (uint64_t)off[n[i]] != nnz[i]) atomicOr(&bad[i], 1u);
     }
+    auto hash = [](uint32_t v, uint32_t w) -> uint64_t {
+        return v < w ? pair_hash(v, w) : (uint64_t)0 - pair_hash(w, v);
+    };
+    const uint32_t l = threadIdx.x & 63u;
     uint32_t dmax = 0;
     const uint64_t rows = rbase[count];
-    for (uint64_t r = gid; r < rows; r += stride) {
-        uint32_t lo = 0, hi = count;  // largest i with rbase[i] <= r
-        while (hi - lo > 1u) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (rbase[mid] <= r) lo = mid;
-            else hi = mid;
+    for (uint64_t base = (gid >> 6) << 6; base < rows; base += stride) {
+        const uint64_t r = base + l;
+        uint32_t i = 0, v = 0, ni = 0, o0 = 0, o1 = 0;
+        bool longrow = false;
+        if (r < rows) {
+            uint32_t lo = 0, hi = count;  // largest i with rbase[i] <= r
+            while (hi - lo > 1u) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (rbase[mid] <= r) lo = mid;
+                else hi = mid;
+            }
+            i = lo;
+            v = (uint32_t)(r - rbase[i]);
+            ni = n[i];
+            const uint32_t* off = offsets + offs_base[i];
+            o0 = off[v];
+            o1 = off[v + 1];
+            uint32_t flags = 0;
+            if (o0 > o1 || (uint64_t)o1 > nnz[i]) {
+                flags |= 1u;
+            } else {
+                const uint32_t d = o1 - o0;
+                dmax = d > dmax ? d : dmax;
+                longrow = d > 32u;
+            }
+            if (!longrow && !flags) {
+                const uint64_t cb = cols_base[i];
+                auto col = [&](uint32_t e) -> uint32_t {
+                    return col_bytes == 2
+                               ? (uint32_t)reinterpret_cast<const uint16_t*>(cols)[cb + e]
+                               : reinterpret_cast<const uint32_t*>(cols)[cb + e];
+                };
+                uint64_t sum = 0;
+                int64_t prev = -1;
+                bool sorted = true;
+                for (uint32_t e = o0; e < o1; ++e) {
+                    const uint32_t w = col(e);
+                    if (w >= ni || w == v) flags |= 2u;
+                    if ((int64_t)w <= prev) sorted = false;
+                    prev = (int64_t)w;
+                    sum += hash(v, w);
+                }
+                if (!sorted)
+                    for (uint32_t e = o0; e < o1; ++e)
+                        for (uint32_t f = e + 1u; f < o1; ++f)
+                            if (col(e) == col(f)) flags |= 4u;
+                if (sum) atomicAdd(&hs[i], (unsigned long long)sum);
+            }
+            if (flags) atomicOr(&bad[i], flags);
         }
-        const uint32_t i = lo;
-        const uint32_t v = (uint32_t)(r - rbase[i]);
-        const uint32_t ni = n[i];
-        const uint32_t* off = offsets + offs_base[i];
-        const uint32_t o0 = off[v], o1 = off[v + 1];
-        uint32_t flags = 0;
-        if (o0 > o1 || (uint64_t)o1 > nnz[i]) {
-            flags |= 1u;
-        } else {
-            const uint32_t d = o1 - o0;
-            dmax = d > dmax ? d : dmax;
-            const uint64_t cb = cols_base[i];
+        uint64_t m = ballot(longrow);
+        while (m) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1ull;
+            const uint32_t ij = shfl(i, j);
+            const uint64_t cb = cols_base[ij];
             auto col = [&](uint32_t e) -> uint32_t {
                 return col_bytes == 2 ? (uint32_t)reinterpret_cast<const uint16_t*>(cols)[cb + e]
                                       : reinterpret_cast<const uint32_t*>(cols)[cb + e];
             };
-            uint64_t sum = 0;
-            int64_t prev = -1;
-            bool sorted = true;
-            for (uint32_t e = o0; e < o1; ++e) {
-                const uint32_t w = col(e);
-                if (w >= ni || w == v) flags |= 2u;
-                if ((int64_t)w <= prev) sorted = false;
-                prev = (int64_t)w;
-                sum += v < w ? pair_hash(v, w) : (uint64_t)0 - pair_hash(w, v);
+            uint64_t acc = 0;
+            const uint32_t res = wave_row_check(shfl(v, j), shfl(ni, j), shfl(o0, j), shfl(o1, j),
+                                                col, hash, tbl, &acc);
+            acc = wave_sum64(acc);
+            if (l == 0) {
+                uint32_t f = 0;
+                if (res & ROWCHK_ENTRY) f |= 2u;
+                if (res & ROWCHK_REPEAT) f |= 4u;
+                if (f) atomicOr(&bad[ij], f);
+                if (acc) atomicAdd(&hs[ij], (unsigned long long)acc);
             }
-            if (!sorted) {
-                if (d <= 512u) {
-                    for (uint32_t e = o0; e < o1; ++e)
-                        for (uint32_t f = e + 1u; f < o1; ++f)
-                            if (col(e) == col(f)) flags |= 4u;
-                } else {
-                    flags |= 8u;
-                }
-            }
-            if (sum) atomicAdd(&hs[i], (unsigned long long)sum);
         }
-        if (flags) atomicOr(&bad[i], flags);
     }
     red[threadIdx.x] = dmax;
     __syncthreads();

@@ -242,4 +242,87 @@ struct Deg {
     }
 };
 
+// ------------------------------------------------------------- row check
+// One wave checks one adjacency row, entries [o0, o1), of vertex v in a graph
+// of ni vertices.  Lanes stride the row: every entry must be below ni and
+// differ from v, and each adds its signed pair hash to the lane's *hs (the
+// callers' symmetry test).  A row that is not strictly increasing is then
+// checked for repeats with an open-addressing table in LDS: ROWCHK_CHUNK
+// entries at a time are inserted (a repeat inside the chunk meets its twin),
+// and the rest of the row is looked up against them.  tbl is this wave's
+// ROWCHK_TBL words of LDS.  Returns ROWCHK_ENTRY and/or ROWCHK_REPEAT, the
+// same on every lane.
+// (4 waves of a block take 16 KB: the validation runs beside a resident
+// search kernel, which leaves 32 KB of LDS per CU to the side stream)
+constexpr uint32_t ROWCHK_TBL = 1024u;    // LDS words per wave
+constexpr uint32_t ROWCHK_CHUNK = 512u;   // entries per pass (load <= 1/2)
+constexpr uint32_t ROWCHK_EMPTY = 0xFFFFFFFFu;
+constexpr uint32_t ROWCHK_ENTRY = 1u;     // an entry out of range or equal to v
+constexpr uint32_t ROWCHK_REPEAT = 2u;    // an entry repeated in the row
+
+__device__ __forceinline__ uint32_t rowchk_slot(uint32_t w) {
+    return (w * 0x9E3779B1u) >> 22;  // 10 bits: ROWCHK_TBL slots
+}
+
+static_assert(4u * 4u * ROWCHK_TBL <= 16384u, "row-check LDS exceeds the serving reserve");
+static_assert(ROWCHK_TBL == 1024u, "rowchk_slot yields 10 bits");
+
+template <typename Col, typename Hash>
+__device__ __forceinline__ uint32_t wave_row_check(uint32_t v, uint32_t ni, uint32_t o0,
+                                                   uint32_t o1, Col col, Hash hash,
+                                                   uint32_t* tbl, uint64_t* hs) {
+    const uint32_t l = threadIdx.x & 63u;
+    uint32_t bad = 0;
+    bool unsorted = false;
+    uint64_t acc = 0;
+    for (uint32_t e = o0 + l; e < o1; e += 64u) {
+        const uint32_t w = col(e);
+        if (w >= ni || w == v) bad |= ROWCHK_ENTRY;
+        if (e > o0 && col(e - 1u) >= w) unsorted = true;
+        acc += hash(v, w);
+    }
+    *hs += acc;
+    if (ballot(unsorted) != 0ull) {
+        for (uint32_t c0 = o0; c0 < o1; c0 += ROWCHK_CHUNK) {
+            const uint32_t c1 = o1 - c0 > ROWCHK_CHUNK ? c0 + ROWCHK_CHUNK : o1;
+            for (uint32_t i = l; i < ROWCHK_TBL; i += 64u) tbl[i] = ROWCHK_EMPTY;
+            wave_sync();
+            for (uint32_t e = c0 + l; e < c1; e += 64u) {
+                const uint32_t w = col(e);
+                if (w == ROWCHK_EMPTY) continue;  // out of range: flagged above
+                uint32_t h = rowchk_slot(w);
+                for (uint32_t p = 0; p < ROWCHK_TBL; ++p) {
+                    const uint32_t prev = atomicCAS(&tbl[h], ROWCHK_EMPTY, w);
+                    if (prev == ROWCHK_EMPTY) break;
+                    if (prev == w) {
+                        bad |= ROWCHK_REPEAT;
+                        break;
+                    }
+                    h = (h + 1u) & (ROWCHK_TBL - 1u);
+                }
+            }
+            wave_sync();
+            for (uint32_t e = c1 + l; e < o1; e += 64u) {
+                const uint32_t w = col(e);
+                uint32_t h = rowchk_slot(w);
+                for (uint32_t p = 0; p < ROWCHK_TBL; ++p) {
+                    const uint32_t t = tbl[h];
+                    if (t == ROWCHK_EMPTY) break;
+                    if (t == w) {
+                        bad |= ROWCHK_REPEAT;
+                        break;
+                    }
+                    h = (h + 1u) & (ROWCHK_TBL - 1u);
+                }
+            }
+            wave_sync();  // lookups done before the next chunk clears tbl
+            if (ballot(bad & ROWCHK_REPEAT) != 0ull) break;
+        }
+    }
+    uint32_t out = 0;
+    if (ballot(bad & ROWCHK_ENTRY) != 0ull) out |= ROWCHK_ENTRY;
+    if (ballot(bad & ROWCHK_REPEAT) != 0ull) out |= ROWCHK_REPEAT;
+    return out;
+}
+
 }  // namespace vc

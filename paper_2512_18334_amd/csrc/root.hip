@@ -56,36 +56,54 @@ __global__ void k_check_offsets(uint32_t n, uint64_t nnz, const uint32_t* off, u
 // of a hash of each unordered pair over all entries vanishes exactly when
 // every entry has its mirror, up to hash collisions)
 template <typename C>
-__global__ void k_check_rows(uint32_t n, const uint32_t* off, const C* col, uint32_t* ctr,
-                             unsigned long long* hsum) {
+__global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* off, const C* col,
+                                                    uint32_t* ctr, unsigned long long* hsum) {
+    // 64 consecutive rows per wave, one per lane; a row longer than 32
+    // entries is checked by the whole wave (wave_row_check)
+    __shared__ uint32_t tbl_all[4 * ROWCHK_TBL];
+    uint32_t* tbl = tbl_all + (threadIdx.x >> 6) * ROWCHK_TBL;
+    const uint32_t l = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
+    auto hash = [](uint32_t v, uint32_t w) -> uint64_t {
+        const uint64_t a = v < w ? v : w, b = v < w ? w : v;
+        const uint64_t h = mix64(a * 0x9E3779B97F4A7C15ull + b);
+        return v < w ? h : (0ull - h);
+    };
+    auto cl = [col](uint32_t e) -> uint32_t { return (uint32_t)col[e]; };
     uint64_t acc = 0;
     uint32_t bad = 0;
-    GRID_LOOP(v, n) {
-        const uint32_t r0 = off[v], r1 = off[v + 1];
-        bool sorted = true;
-        for (uint32_t e = r0; e < r1; ++e) {
-            uint32_t w = (uint32_t)col[e];
-            if (w >= n) { bad |= 4u; continue; }
-            if (w == v) bad |= 8u;
-            if (e > r0 && (uint32_t)col[e - 1] >= w) sorted = false;
-            uint64_t a = v < w ? v : w, b = v < w ? w : v;
-            uint64_t h = mix64(a * 0x9E3779B97F4A7C15ull + b);
-            acc += v < w ? h : (0ull - h);
-        }
-        if (!sorted) {
-            if (r1 - r0 <= 512u) {
+    for (uint32_t base = wave * 64u; base < n; base += waves * 64u) {
+        const uint32_t v = base + l;
+        const uint32_t r0 = v < n ? off[v] : 0u, r1 = v < n ? off[v + 1] : 0u;
+        const bool longrow = r1 - r0 > 32u;
+        if (v < n && !longrow) {
+            bool sorted = true;
+            for (uint32_t e = r0; e < r1; ++e) {
+                const uint32_t w = (uint32_t)col[e];
+                if (w >= n) { bad |= 4u; continue; }
+                if (w == v) bad |= 8u;
+                if (e > r0 && (uint32_t)col[e - 1] >= w) sorted = false;
+                acc += hash(v, w);
+            }
+            if (!sorted)
                 for (uint32_t e = r0; e < r1; ++e)
                     for (uint32_t f = e + 1; f < r1; ++f)
                         if (col[e] == col[f]) bad |= 16u;
-            } else {
-                bad |= 32u;  // long unsorted row: repeated entries not checked
-            }
+        }
+        uint64_t m = ballot(longrow);
+        while (m) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1ull;
+            const uint32_t r = wave_row_check(base + j, n, shfl(r0, j), shfl(r1, j), cl, hash,
+                                              tbl, &acc);
+            if (r & ROWCHK_ENTRY) bad |= 4u;
+            if (r & ROWCHK_REPEAT) bad |= 16u;
         }
     }
-    if (bad & ~32u) atomicOr(&ctr[CTR_INVALID], bad & ~32u);
-    if (bad & 32u) atomicOr(&ctr[CTR_UNCHECKED], 1u);
+    if (bad) atomicOr(&ctr[CTR_INVALID], bad);
     acc = wave_sum64(acc);
-    if ((threadIdx.x & 63u) == 0 && acc) atomicAdd(hsum, (unsigned long long)acc);
+    if (l == 0 && acc) atomicAdd(hsum, (unsigned long long)acc);
 }
 
 // ------------------------------------------------------------- degrees

@@ -9,7 +9,6 @@ namespace vc {
 // device counters (uint32 slots of RootBufs::ctr)
 enum {
     CTR_INVALID = 0,    // validation failure bits
-    CTR_UNCHECKED = 1,  // long unsorted rows whose repeats were not checked
     CTR_SROOT = 2,      // vertices the root reduction put in the cover
     CTR_FIRED = 4,      // rule firings of the last two rounds (2 slots)
     CTR_GLIVE = 6,      // greedy: live vertices seen this round (2 slots)

@@ -154,6 +154,8 @@ vc_status Server::plan() {
     vc_status pw = plan_workers(c, n_pad, deg_bytes, &lp, &gwords, &w);
     if (pw) return pw;
     // leave LDS on every CU for the root-step kernels of the side stream
+    // (they take at most 16 KB per block: a kernel that cannot be placed
+    // beside the resident search would wait for it forever)
     if (lp.bytes > 128u * 1024u && gwords > 4096u) {
         gwords -= std::min<uint32_t>(gwords - 4096u, (lp.bytes - 128u * 1024u + 3u) / 4u);
         lp = lds_plan(n_pad, deg_bytes, gwords);

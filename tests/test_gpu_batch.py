@@ -115,6 +115,18 @@ def test_batch_device_validation_rejects(solver):
     assert e.value.status == vc.VC_EINVAL
 
 
+def test_batch_device_validation_finds_repeats_in_long_rows(solver):
+    from tests.test_gpu_parity import long_row_graph
+    good = long_row_graph(1500, seed=3)
+    bad = long_row_graph(1500, dup=(7, 1300), seed=3)
+    r = solver.mvc_batch(vc.Batch.from_graphs([gg.cycle(5), good]).to_device("cuda:0"))
+    assert [int(x) for x in r.sizes] == [3, solver.mvc(good).size]
+    b = vc.Batch.from_graphs([gg.cycle(5), bad, gg.path(4)]).to_device("cuda:0")
+    with pytest.raises(vc.VCError) as e:
+        solver.mvc_batch(b)
+    assert e.value.status == vc.VC_EINVAL
+
+
 def test_batch_node_limit_is_per_instance(libvc, orc):
     """A tiny limit stops the hard instances only; the easy ones still
     return exact sizes, and every cover is valid."""

@@ -130,6 +130,46 @@ def test_device_validation_rejects(solver):
     assert e.value.status == vc.VC_EINVAL
 
 
+def long_row_graph(deg, dup=None, seed=0):
+    """Two adjacent hubs (0 and 1) joined to `deg` - 1 leaves that form a
+    path; the hub rows are shuffled (not sorted).  dup=(p1, p2): hub 1 sits
+    at positions p1 and p2 of hub 0's row, and hub 0 twice in hub 1's row --
+    a symmetric repeat that only the check of long rows can catch."""
+    r = np.random.default_rng(seed)
+    n = deg + 1
+    leaves = np.arange(2, n)
+    h0 = [int(x) for x in r.permutation(leaves)]
+    h1 = [int(x) for x in r.permutation(np.append(leaves, 0))]
+    if dup is None:
+        h0.insert(int(r.integers(0, len(h0) + 1)), 1)
+    else:
+        h0.insert(dup[0], 1)
+        h0.insert(dup[1], 1)
+        h1.insert(int(r.integers(0, len(h1) + 1)), 0)
+    rows = [h0, h1]
+    for x in range(2, n):
+        rows.append([0, 1] + ([x - 1] if x > 2 else []) + ([x + 1] if x < n - 1 else []))
+    offsets = np.zeros(n + 1, np.uint32)
+    offsets[1:] = np.cumsum([len(a) for a in rows])
+    return gg.Graph(n, offsets, np.concatenate(rows).astype(np.uint32), name=f"hubs2x{deg}")
+
+
+@pytest.mark.parametrize("deg,dup", [(700, (3, 650)), (1500, (5, 1400)), (1500, (1100, 1300)),
+                                     (2600, (2500, 2599))])
+def test_device_validation_finds_repeats_in_long_unsorted_rows(solver, orc, deg, dup):
+    good = long_row_graph(deg, seed=deg)
+    r = solver.mvc(vc.DeviceGraph.from_graph(good))
+    assert r.size == orc.mvc(good)["size"]
+    bad = long_row_graph(deg, dup=dup, seed=deg)
+    assert vc.DeviceGraph.from_graph(bad).n == good.n
+    with pytest.raises(vc.VCError) as e:
+        solver.mvc(vc.DeviceGraph.from_graph(bad))
+    assert e.value.status == vc.VC_EINVAL
+    with pytest.raises(vc.VCError) as e:  # the host check agrees
+        solver.mvc(bad)
+    assert e.value.status == vc.VC_EINVAL
+
+
 # ------------------------------------------- component-splitting workload
 
 def test_blocks_hubs_small(solver, orc):
@@ -188,9 +228,7 @@ def test_no_induce_searches_the_input_graph(orc, libvc):
         a = g0.n + extra + 2 * i
         us += [i * 3, a]
         vs += [a, a + 1]
-    src = np.repeat(np.arange(g0.n), np.diff(g0.offsets.astype(np.int64)))
-    keep = src < g0.cols
-    eu, ev = src[keep], g0.cols[keep].astype(np.int64)
+    eu, ev = g0.edges()
     g = gg.from_edges(g0.n + extra + 16, np.concatenate([eu, us]), np.concatenate([ev, vs]))
     e = orc.mvc(g)["size"]
     with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000) as s0:
@@ -203,6 +241,23 @@ def test_no_induce_searches_the_input_graph(orc, libvc):
             assert r.stats["n_kernel"] == g.n
             for k in (e - 1, e):
                 assert s.pvc(g, k).yes == (e <= k)
+
+
+def test_cycle_breakdown_counts_every_activity(solver, orc):
+    """The per-activity shader-cycle counters (Fig. 4) are filled on a graph
+    that branches on vertices and on components, and they add up to no more
+    than the workers' lifetime."""
+    g = gg.config2_blocks_hubs(seed=23, nblocks=8, bsize=64, nhubs=4, per_block=14)
+    r = gpu_mvc(solver, g, orc.mvc(g)["size"])
+    cyc = r.stats["cycles"]
+    assert list(cyc) == vc.CYCLE_NAMES
+    for k in ("fetch", "reduce", "components", "branch", "complete"):
+        assert cyc[k] > 0, (k, cyc)
+    assert r.stats["component_branches"] > 0
+    # shader clock at most 2.4 GHz: the sum over workers is bounded by
+    # workers x kernel time
+    bound = r.stats["workers"] * r.stats["ms_search"] * 1e-3 * 2.5e9
+    assert sum(cyc.values()) <= bound, (sum(cyc.values()), bound)
 
 
 def _hub_graph(hub_degree, seed):
