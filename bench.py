@@ -309,7 +309,8 @@ def bench_serve(args, torch, gg, vc):
 
 
 ABLATIONS = [("proposed", 0), ("no_components", 1), ("no_reduce_induce", 32),
-             ("no_compaction", 64), ("no_load_balance", 2), ("no_small_solver", 16)]
+             ("no_compaction", 64), ("no_load_balance", 2), ("no_small_solver", 16),
+             ("crown_forced", 128)]
 
 
 def bench_ablation(args, torch, gg, vc):

@@ -81,6 +81,12 @@ typedef struct {
                                    instead of filtering the previous list
                                    (bounding of non-zero entries off,
                                    Table II)                                */
+#define VC_OPT_CROWN 128u       /* single solves: run the crown reduction at
+                                   the root whatever the size (by default it
+                                   runs when the degree rules leave at least
+                                   4096 vertices)                           */
+#define VC_OPT_NO_CROWN 256u    /* single solves: never run the crown
+                                   reduction                                */
 
 /*
  * Tuning knobs.  Zero in any field selects the library default.
@@ -165,6 +171,9 @@ typedef struct {
     double ms_induce;            /* device time: induce + plan readback     */
     double ms_search;            /* device time: persistent search          */
     double ms_total;             /* wall time of the whole call             */
+    uint32_t crown_cover;        /* vertices crowns put in the cover (|H|)  */
+    uint32_t crown_removed;      /* vertices crowns removed (|I|)           */
+    uint32_t crown_rounds;       /* crowns found at the root                */
 } vc_stats;
 
 typedef struct vc_ctx vc_ctx;

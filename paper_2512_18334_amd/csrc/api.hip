@@ -96,6 +96,10 @@ vc_status plan_workers(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* l
 
 namespace {
 
+// the crown reduction runs by default when the degree rules leave at least
+// this many vertices (smaller kernels are cheaper to search than to match)
+constexpr uint32_t CROWN_AUTO_MIN = 4096;
+
 vc_status device_validate(vc_ctx* c, const RootGraph& rg) {
     HIPCHK(ensure(c->ctr, CTR_COUNT * 4));
     HIPCHK(ensure(c->hsum, 8));
@@ -277,7 +281,38 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     HIPCHK(hipMemcpyAsync(&hdr[0], b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const uint32_t np = hdr[0], dmax = hdr[1];
+    uint32_t np = hdr[0], dmax = hdr[1];
+    // crown reductions (Sec. IV-B), each followed by the degree rules again,
+    // while crowns are found: by default on large kernels only
+    const uint32_t fl = c->opts.flags;
+    const bool crown = !no_induce && !(fl & VC_OPT_NO_CROWN) &&
+                       np >= ((fl & VC_OPT_CROWN) ? 2u : CROWN_AUTO_MIN);
+    for (uint32_t it = 0; crown && np >= 2u && it < 16u; ++it) {
+        HIPCHK(ensure(c->crown, 32ull * rg.n));
+        b.cw = (uint32_t*)c->crown.p;
+        uint32_t h = 0;
+        HIPCHK(root_crown(rg, b, s, &h));
+        if (h == 0) break;
+        ++stv.crown_rounds;
+        stv.crown_cover += h;
+        uint32_t r2 = 0;
+        HIPCHK(root_reduce(rg, b, best0, s, 1u << 16, &r2));
+        stv.root_rounds += r2;
+        HIPCHK(hipMemcpyAsync(&sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&stv.crown_removed, b.ctr + CTR_CROWN_I, 4, hipMemcpyDeviceToHost,
+                              s));
+        HIPCHK(hipEventRecord(c->ev[1], s));
+        HIPCHK(hipStreamSynchronize(s));
+        stv.forced_root = sroot;
+        if ((int)sroot >= best0) return pvc ? finish_no() : finish_with_greedy(1);
+        HIPCHK(hipMemsetAsync(b.ctr + CTR_MAXDEG, 0, 4, s));  // raised by atomicMax
+        HIPCHK(root_induce_a(rg, b, s, false));
+        HIPCHK(hipMemcpyAsync(&hdr[0], b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        np = hdr[0];
+        dmax = hdr[1];
+    }
     stv.n_kernel = np;
     stv.max_degree_kernel = dmax;
     const int kbest0 = best0 - (int)sroot;

@@ -74,7 +74,7 @@ struct vc_ctx {
     // input copies (host CSR) and root buffers
     vc::DevBuf in_off, in_col;
     vc::DevBuf rdeg, gdeg, gin, addf, newly, flags, newid, oldid, kdeg, koff, kcol, cover,
-        scan_tmp, ctr, hsum;
+        scan_tmp, ctr, hsum, crown;
     // search buffers
     vc::DevBuf stacks, wl_slots, wl_seq, ctl, reg, bitmaps, arena;
     // batch buffers: descriptors, per-instance state and results

@@ -382,13 +382,48 @@ template <typename C, typename CO>
 __global__ void k_induce_cols(uint32_t np, const uint32_t* off, const C* col,
                               const uint32_t* rdeg, const uint32_t* newid,
                               const uint32_t* oldid, const uint32_t* koff, CO* kcol) {
-    GRID_LOOP(i, np) {
-        const uint32_t v = oldid[i];
-        uint32_t pos = koff[i];
-        const uint32_t end = koff[i + 1];
-        for (uint32_t e = off[v]; e < off[v + 1] && pos < end; ++e) {
-            uint32_t u = (uint32_t)col[e];
-            if (rlive(rdeg[u])) kcol[pos++] = (CO)newid[u];
+    // 64 consecutive new vertices per wave, one per lane; a row longer than
+    // 32 entries is compacted by the whole wave (ballot + mbcnt keep order)
+    const uint32_t l = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t base = wave * 64u; base < np; base += waves * 64u) {
+        const uint32_t i = base + l;
+        uint32_t r0 = 0, r1 = 0;
+        if (i < np) {
+            const uint32_t v = oldid[i];
+            r0 = off[v];
+            r1 = off[v + 1];
+        }
+        const bool longrow = r1 - r0 > 32u;
+        if (i < np && !longrow) {
+            uint32_t pos = koff[i];
+            const uint32_t end = koff[i + 1];
+            for (uint32_t e = r0; e < r1 && pos < end; ++e) {
+                const uint32_t u = (uint32_t)col[e];
+                if (rlive(rdeg[u])) kcol[pos++] = (CO)newid[u];
+            }
+        }
+        uint64_t m = ballot(longrow);
+        while (m) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1ull;
+            const uint32_t a = shfl(r0, j), b = shfl(r1, j);
+            uint32_t pos = koff[base + j];
+            const uint32_t end = koff[base + j + 1];
+            for (uint32_t c = a; c < b; c += 64u) {
+                const uint32_t e = c + l;
+                uint32_t u = 0;
+                bool keep = false;
+                if (e < b) {
+                    u = (uint32_t)col[e];
+                    keep = rlive(rdeg[u]);
+                }
+                const uint64_t km = ballot(keep);
+                const uint32_t at = pos + mbcnt(km);
+                if (keep && at < end) kcol[at] = (CO)newid[u];
+                pos += (uint32_t)__builtin_popcountll(km);
+            }
         }
     }
 }

@@ -14,7 +14,12 @@ enum {
     CTR_GLIVE = 6,      // greedy: live vertices seen this round (2 slots)
     CTR_GSIZE = 8,      // greedy cover size
     CTR_MAXDEG = 9,     // maximum degree of the induced subgraph
-    CTR_COUNT = 16
+    CTR_CROWN_F = 10,   // crown: three rotating BFS frontier sizes
+    CTR_CROWN_E = 13,   // crown: augmenting paths found this phase
+    CTR_CROWN_M = 14,   // crown: vertices matched by the last proposal rounds
+    CTR_CROWN_H = 15,   // crown: |H| of the last crown
+    CTR_CROWN_I = 16,   // crown: |I| summed over the crowns of a solve
+    CTR_COUNT = 24
 };
 
 struct RootGraph {
@@ -41,6 +46,7 @@ struct RootBufs {
     uint32_t* scan_tmp;  // [n / 2048 + 2]
     uint32_t* ctr;       // [CTR_COUNT]
     unsigned long long* hsum;
+    uint32_t* cw = nullptr;  // [8n] crown workspace
 };
 
 hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* hsum,
@@ -56,6 +62,9 @@ hipError_t root_induce_b(const RootGraph& g, const RootBufs& b, uint32_t np, uin
                          hipStream_t st);
 hipError_t root_cover(const RootGraph& g, const RootBufs& b, uint32_t np, int improved,
                       const uint32_t* root_bitmap, hipStream_t st);
+// One crown reduction (crown.hip): H into the cover (counted in
+// CTR_SROOT), I removed, their edges dropped.  *h_out = |H| (0: no crown).
+hipError_t root_crown(const RootGraph& g, const RootBufs& b, hipStream_t st, uint32_t* h_out);
 hipError_t scan_u32(const uint32_t* in, uint32_t N, uint32_t* out, uint32_t* tmp,
                     hipStream_t st);
 

@@ -27,6 +27,8 @@ VC_OPT_NO_GRAPH = 8
 VC_OPT_NO_SMALL = 16
 VC_OPT_NO_INDUCE = 32
 VC_OPT_NO_COMPACT = 64
+VC_OPT_CROWN = 128
+VC_OPT_NO_CROWN = 256
 VC_MIN, VC_PARAM = 0, 1
 
 CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]
@@ -83,7 +85,9 @@ class vc_stats(ctypes.Structure):
                 ("root_rounds", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint32),
                 ("bitmap_bytes", ctypes.c_uint32), ("ms_root", ctypes.c_double),
                 ("ms_induce", ctypes.c_double), ("ms_search", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double),
+                ("crown_cover", ctypes.c_uint32), ("crown_removed", ctypes.c_uint32),
+                ("crown_rounds", ctypes.c_uint32)]
 
 
 class VCError(RuntimeError):

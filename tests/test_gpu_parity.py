@@ -207,6 +207,7 @@ def test_ablation_switches_agree(solver, orc, libvc):
                dict(flags=vc.VC_OPT_NO_COMPONENTS | vc.VC_OPT_NO_SMALL),
                dict(flags=vc.VC_OPT_NO_INDUCE), dict(flags=vc.VC_OPT_NO_COMPACT),
                dict(flags=vc.VC_OPT_NO_INDUCE | vc.VC_OPT_NO_COMPACT | vc.VC_OPT_NO_SMALL),
+               dict(flags=vc.VC_OPT_CROWN), dict(flags=vc.VC_OPT_NO_CROWN),
                dict(workers=1), dict(workers=3),
                dict(registry_cap=64), dict(worklist_cap=8)]:
         with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000, **kw) as s2:
