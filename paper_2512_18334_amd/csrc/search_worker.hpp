@@ -1191,17 +1191,17 @@ struct Worker {
         }
         if (l == 0) st_coh(&g[size], carry);
         wave_sync();
-        // columns: each lane copies the live part of its vertices' rows
+        // columns: the component's rows spread over the lanes (for_rows);
+        // each live entry takes the next place of its row (CUR: row cursors,
+        // so the order inside a row is arbitrary)
         uint32_t* gc = g + size + 1u;
-        for (uint32_t i = l; i < size; i += 64) {
-            const uint32_t v = Q[a + i];
-            uint32_t pos = CUR[i];
-            const uint32_t r1 = vo(v + 1);
-            for (uint32_t e = vo(v); e < r1; ++e) {
-                const uint32_t w = vc(e);
-                if (DG::live(DG::get(deg, w))) st_coh(&gc[pos++], M[w]);
-            }
-        }
+        for_rows([&](uint32_t x) { return vo(x); }, [&](uint32_t e) { return vc(e); }, Q + a, size,
+                 MK, [&](bool ok, uint32_t x, uint32_t w) {
+                     if (ok && DG::live(DG::get(deg, w))) {
+                         const uint32_t pos = atomicAdd(&CUR[M[x]], 1u);
+                         st_coh(&gc[pos], M[w]);
+                     }
+                 });
         wave_sync();
         return (uint32_t)at;
     }
