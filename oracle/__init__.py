@@ -46,6 +46,9 @@ def _load():
                                ctypes.c_uint64, u32p, u32p, u64p, u32p]
     lib.oracle_greedy.restype = ctypes.c_int64
     lib.oracle_greedy.argtypes = [ctypes.c_uint32, u32p, u32p, u32p, u32p]
+    lib.oracle_enum_minimal.restype = ctypes.c_int64
+    lib.oracle_enum_minimal.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint32,
+                                        ctypes.c_uint64, u32p, u32p, ctypes.c_uint64]
     _lib = lib
     return lib
 
@@ -115,3 +118,23 @@ def greedy(g):
     r = _load().oracle_greedy(n, _ptr(off), _ptr(col), _ptr(cover),
                               ctypes.byref(clen))
     return {"size": int(r), "cover": cover[:clen.value].copy()}
+
+
+def enum_minimal(g, k: int, cap: int = 1_000_000, node_limit: int = 0):
+    """All minimal vertex covers of g with at most k vertices, as a set of
+    frozensets of vertex ids (exactly the first `cap` found are returned;
+    "count" is the total)."""
+    off, col = _prep(g.offsets, g.cols)
+    n = int(g.n)
+    kk = max(int(k), 1)
+    ids = np.zeros(max(cap * kk, 1), np.uint32)
+    lens = np.zeros(max(cap, 1), np.uint32)
+    r = _load().oracle_enum_minimal(n, _ptr(off), _ptr(col), int(k), cap, _ptr(ids),
+                                    _ptr(lens), node_limit)
+    if r == -2:
+        raise OracleLimit(f"node limit {node_limit} reached")
+    if r < 0:
+        raise MemoryError("oracle allocation failed")
+    got = min(int(r), cap)
+    covers = {frozenset(ids[c * kk:c * kk + int(lens[c])].tolist()) for c in range(got)}
+    return {"count": int(r), "covers": covers}

@@ -650,3 +650,150 @@ int64_t oracle_greedy(uint32_t n, const uint32_t *off, const uint32_t *col,
     free(cg);
     return s;
 }
+
+/* ------------------------------------------------------------------------
+ * Enumeration of the minimal vertex covers of size <= k (the PVC variant
+ * that Sec. III-E describes but the paper does not build).  Reading taken:
+ * "all covers of size <= k" is represented by its minimal members; every
+ * cover of size <= k contains one of them.  A cover C is minimal when every
+ * vertex of C has a neighbour outside C.
+ *
+ * Plain enumeration from that definition: take the lowest-id vertex u with an
+ * edge to a vertex outside C (an uncovered edge {u, w}); either u joins C, or
+ * u stays out for good and all of N(u) joins C (a branch that would put an
+ * excluded vertex into C is dropped).  Every assignment reached is
+ * consistent, so no set is reached twice, and following a minimal cover C*
+ * (u in C* or not) reaches C* itself; a leaf (no uncovered edge) is kept
+ * when it is minimal.  Branches with |C| > k are cut.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    const graph_t *g;
+    uint32_t k;
+    uint8_t *in;  /* 1: in C */
+    uint8_t *out; /* 1: kept out of C */
+    uint32_t size;
+    uint64_t found, cap; /* covers found; covers that fit in ids/offs */
+    uint32_t *ids;       /* cap * k ids */
+    uint32_t *lens;      /* cap lengths */
+    uint64_t nodes, node_limit;
+    int over; /* node limit reached */
+} enum_t;
+
+static int enum_minimal_leaf(const enum_t *e)
+{
+    const graph_t *g = e->g;
+    for (uint32_t v = 0; v < g->n; ++v) {
+        if (!e->in[v])
+            continue;
+        int has_out = 0;
+        for (uint32_t i = g->off[v]; i < g->off[v + 1]; ++i)
+            if (!e->in[g->col[i]]) {
+                has_out = 1;
+                break;
+            }
+        if (!has_out)
+            return 0;
+    }
+    return 1;
+}
+
+static void enum_rec(enum_t *e)
+{
+    const graph_t *g = e->g;
+    if (e->over)
+        return;
+    if (e->node_limit && ++e->nodes > e->node_limit) {
+        e->over = 1;
+        return;
+    }
+    if (e->size > e->k)
+        return;
+    /* lowest u with an uncovered edge */
+    uint32_t u = g->n;
+    for (uint32_t v = 0; v < g->n && u == g->n; ++v) {
+        if (e->in[v])
+            continue;
+        for (uint32_t i = g->off[v]; i < g->off[v + 1]; ++i)
+            if (!e->in[g->col[i]]) {
+                u = v;
+                break;
+            }
+    }
+    if (u == g->n) {
+        if (enum_minimal_leaf(e)) {
+            if (e->found < e->cap) {
+                uint32_t c = 0;
+                for (uint32_t v = 0; v < g->n; ++v)
+                    if (e->in[v])
+                        e->ids[e->found * e->k + c++] = v;
+                e->lens[e->found] = c;
+            }
+            ++e->found;
+        }
+        return;
+    }
+    /* u joins C */
+    e->in[u] = 1;
+    ++e->size;
+    enum_rec(e);
+    e->in[u] = 0;
+    --e->size;
+    /* u stays out: N(u) joins C, unless one of them was kept out */
+    for (uint32_t i = g->off[u]; i < g->off[u + 1]; ++i)
+        if (e->out[g->col[i]])
+            return;
+    uint32_t added = 0;
+    uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (g->off[u + 1] - g->off[u] + 1));
+    if (!list) {
+        e->over = 2;
+        return;
+    }
+    for (uint32_t i = g->off[u]; i < g->off[u + 1]; ++i) {
+        uint32_t w = g->col[i];
+        if (!e->in[w]) {
+            e->in[w] = 1;
+            list[added++] = w;
+        }
+    }
+    e->out[u] = 1;
+    e->size += added;
+    enum_rec(e);
+    e->size -= added;
+    e->out[u] = 0;
+    for (uint32_t i = 0; i < added; ++i)
+        e->in[list[i]] = 0;
+    free(list);
+}
+
+/* oracle_enum_minimal: number of minimal covers of size <= k (-2: node limit,
+ * -1: allocation); the first `cap` of them go to ids[c*k ..] (ascending) and
+ * lens[c]. */
+int64_t oracle_enum_minimal(uint32_t n, const uint32_t *off, const uint32_t *col, uint32_t k,
+                            uint64_t cap, uint32_t *ids, uint32_t *lens, uint64_t node_limit)
+{
+    graph_t g = {n, off, col};
+    enum_t e;
+    memset(&e, 0, sizeof e);
+    e.g = &g;
+    e.k = k;
+    e.cap = cap;
+    e.ids = ids;
+    e.lens = lens;
+    e.node_limit = node_limit;
+    e.in = (uint8_t *)calloc(n ? n : 1, 1);
+    e.out = (uint8_t *)calloc(n ? n : 1, 1);
+    if (!e.in || !e.out) {
+        free(e.in);
+        free(e.out);
+        return -1;
+    }
+    enum_rec(&e);
+    free(e.in);
+    free(e.out);
+    if (e.over == 2)
+        return -1;
+    if (e.over)
+        return -2;
+    return (int64_t)e.found;
+}
