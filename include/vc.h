@@ -217,6 +217,30 @@ vc_status vc_param(vc_ctx *ctx, const vc_csr *g, uint32_t k, int *yes,
                    uint32_t *cover, uint32_t *cover_len);
 
 /*
+ * Enumeration variant of PVC (described in Sec. III-E, not built in the
+ * paper): all minimal vertex covers of size <= k.  Every cover of size <= k
+ * contains one of them (a cover is minimal when each of its vertices has a
+ * neighbour outside it).  They are enumerated per connected component, each
+ * within k minus a lower bound of the other components, and combined on the
+ * device.
+ *   *count       the number of minimal covers of size <= k (saturates at
+ *                UINT64_MAX; exact below it)
+ *   covers       (host, capacity max_covers * k) cover t at covers[t * k],
+ *                its ids ascending, t < min(*count, max_covers); the order
+ *                of the covers is unspecified.  May be NULL when k = 0.
+ *   sizes        (host, capacity max_covers) the length of cover t.
+ *                May be NULL when max_covers = 0 (count only).
+ * A graph without edges has one minimal cover, the empty set.  Limits: every
+ * connected component has at most 64 vertices, at most 2^26 covers are
+ * listed over all components, and (components + 1) * (k + 1) <= 2^26
+ * (VC_ERANGE otherwise); vc_opts.node_limit bounds each component's
+ * enumeration (VC_ETIMEDOUT).  VC_EAGAIN while served requests are in
+ * flight.
+ */
+vc_status vc_param_enum(vc_ctx *ctx, const vc_csr *g, uint32_t k, uint64_t max_covers,
+                        uint32_t *covers, uint32_t *sizes, uint64_t *count);
+
+/*
  * A batch of independent graphs packed into one offsets buffer and one cols
  * buffer.  Instance i is the CSR (as for vc_csr) with
  *   offsets[offs_base[i] .. offs_base[i] + n[i]]   (offsets[offs_base[i]] = 0,

@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 # (source, object name, extra flags); the search worker is built once per
 # degree-array type so the three instantiations compile in parallel
 SOURCES = [("api.hip", "api", []), ("batch.hip", "batch", []), ("root.hip", "root", []),
-           ("crown.hip", "crown", []),
+           ("crown.hip", "crown", []), ("enum.hip", "enum", []),
            ("search.hip", "search", []), ("serve.hip", "serve", []),
            ("search_deg.hip", "search_d1", ["-DVC_DEG_BYTES=1"]),
            ("search_deg.hip", "search_d2", ["-DVC_DEG_BYTES=2"]),

@@ -500,6 +500,8 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
 
 namespace vc {
 
+vc_status stage_input(vc_ctx* c, const vc_csr* g, RootGraph* rg) { return stage_graph(c, g, rg); }
+
 vc_status solve_one(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, uint32_t* size, int* yes,
                     uint32_t* cover, uint32_t* cover_len) {
     if (pvc && k > 0x3FFFFFF0u) k = 0x3FFFFFF0u;

@@ -86,9 +86,14 @@ struct vc_ctx {
     // serving (vc_submit): created on the first request
     vc::Server* srv = nullptr;
     hipEvent_t ev[6] = {};
+    // enumeration of minimal covers (vc_param_enum)
+    vc::DevBuf en[13];
 };
 
 namespace vc {
+struct RootGraph;
+// Place a graph on the device (uploading a host CSR) and validate it.
+vc_status stage_input(vc_ctx* c, const vc_csr* g, RootGraph* rg);
 // Exact host-side check of a host CSR against the rules stated in vc.h.
 vc_status validate_host(const vc_csr* g);
 vc_status check_args(const vc_csr* g);

@@ -1,0 +1,444 @@
+// Enumeration of the minimal vertex covers of size <= k: the PVC variant
+// that Sec. III-E describes (enumerate per component, then combine the
+// components' covers whose sizes fit) and the paper leaves unbuilt.  All
+// covers of size <= k are the supersets of these.
+//
+// Steps, all on the device:
+//   1. connected components by min-label propagation with pointer jumping;
+//      component ids by a scan of the roots; a local id (0..63) per vertex;
+//   2. per component, one wave: adjacency masks, a greedy matching (a lower
+//      bound lb_c on its cover size); the component's budget is
+//      k - sum of the other components' lb (a cover of the whole graph within
+//      k leaves no more room than that);
+//   3. per component, one wave enumerates its minimal covers within the
+//      budget (twice: counting by size, then writing the masks): branch on
+//      the lowest vertex u with an uncovered edge, u in the cover, or u out
+//      for good and N(u) in (dropped if N(u) meets a vertex kept out); keep
+//      a leaf when every cover vertex has a neighbour outside;
+//   4. ways[c][b] = number of ways to pick one cover from each of components
+//      c.. with total size <= b (saturating); the count is ways[0][k];
+//   5. cover t of the combined list is unranked component by component.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "ctx.hpp"
+#include "dev_common.hpp"
+#include "internal.hpp"
+#include "root.hpp"
+#include "vc.h"
+
+namespace vc {
+
+namespace {
+
+constexpr uint32_t EN_NONE = 0xFFFFFFFFu;
+constexpr uint32_t EN_MAXC = 64;                 // vertices per component
+constexpr uint64_t EN_LIST_MAX = 1ull << 26;     // component covers kept
+constexpr uint64_t EN_WAYS_MAX = 1ull << 26;     // (components + 1) x (k + 1)
+constexpr uint64_t EN_SAT = ~0ull;
+
+#define EN_GRID_LOOP(i, n) \
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
+
+__device__ __forceinline__ uint64_t rl64(uint64_t x, uint32_t j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b) {
+    if (a == 0 || b == 0) return 0;
+    return b > EN_SAT / a ? EN_SAT : a * b;
+}
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
+    return a > EN_SAT - b ? EN_SAT : a + b;
+}
+
+// ---------------------------------------------------------------- labels
+
+__global__ void k_en_label_init(uint32_t n, const uint32_t* off, uint32_t* label) {
+    EN_GRID_LOOP(v, n) label[v] = off[v + 1] > off[v] ? v : EN_NONE;
+}
+
+template <typename C>
+__global__ void k_en_label_prop(uint32_t n, const uint32_t* off, const C* col, uint32_t* label,
+                                uint32_t* changed) {
+    uint32_t ch = 0;
+    EN_GRID_LOOP(v, n) {
+        const uint32_t lv = label[v];
+        if (lv == EN_NONE) continue;
+        uint32_t m = lv;
+        for (uint32_t e = off[v]; e < off[v + 1]; ++e) {
+            const uint32_t lu = label[(uint32_t)col[e]];
+            m = lu < m ? lu : m;
+        }
+        m = label[m] < m ? label[m] : m;  // pointer jumping
+        if (m < lv) {
+            atomicMin(&label[v], m);
+            ++ch;
+        }
+    }
+    ch = wave_sum(ch);
+    if ((threadIdx.x & 63u) == 0 && ch) atomicAdd(changed, ch);
+}
+
+__global__ void k_en_roots(uint32_t n, const uint32_t* label, uint32_t* flag) {
+    EN_GRID_LOOP(v, n) flag[v] = label[v] == v ? 1u : 0u;
+}
+
+// local id of every vertex in its component; size of every component
+__global__ void k_en_local(uint32_t n, const uint32_t* label, const uint32_t* rank,
+                           uint32_t* loc, uint32_t* csize, uint32_t* maxsize) {
+    uint32_t mx = 0;
+    EN_GRID_LOOP(v, n) {
+        const uint32_t lv = label[v];
+        if (lv == EN_NONE) continue;
+        const uint32_t c = rank[lv];
+        const uint32_t i = atomicAdd(&csize[c], 1u);
+        loc[v] = i;
+        mx = i + 1u > mx ? i + 1u : mx;
+    }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63u) == 0 && mx) atomicMax(maxsize, mx);
+}
+
+__global__ void k_en_place(uint32_t n, const uint32_t* label, const uint32_t* rank,
+                           const uint32_t* loc, const uint32_t* coff, uint32_t* verts) {
+    EN_GRID_LOOP(v, n) {
+        const uint32_t lv = label[v];
+        if (lv == EN_NONE) continue;
+        verts[coff[rank[lv]] + loc[v]] = v;
+    }
+}
+
+// ------------------------------------------------------------ per component
+
+// lane i < nc: local vertex i's adjacency mask
+template <typename C>
+__device__ __forceinline__ uint64_t en_adj(const uint32_t* off, const C* col, const uint32_t* loc,
+                                           const uint32_t* verts, uint32_t base, uint32_t nc) {
+    const uint32_t l = threadIdx.x & 63u;
+    uint64_t a = 0;
+    if (l < nc) {
+        const uint32_t v = verts[base + l];
+        for (uint32_t e = off[v]; e < off[v + 1]; ++e) a |= 1ull << loc[(uint32_t)col[e]];
+    }
+    return a;
+}
+
+// greedy maximal matching size: a lower bound on the component's cover
+template <typename C>
+__global__ void __launch_bounds__(64) k_en_lb(uint32_t ncomp, const uint32_t* off, const C* col,
+                                              const uint32_t* loc, const uint32_t* verts,
+                                              const uint32_t* coff, uint32_t* lb, uint32_t* lbsum) {
+    for (uint32_t c = blockIdx.x; c < ncomp; c += gridDim.x) {
+        const uint32_t base = coff[c], nc = coff[c + 1] - base;
+        const uint64_t adj = en_adj(off, col, loc, verts, base, nc);
+        uint64_t matched = 0;
+        uint32_t m = 0;
+        for (uint32_t i = 0; i < nc; ++i) {
+            if ((matched >> i) & 1ull) continue;
+            const uint64_t a = rl64(adj, i) & ~matched;
+            if (a) {
+                matched |= (1ull << i) | (1ull << __builtin_ctzll(a));
+                ++m;
+            }
+        }
+        if (threadIdx.x == 0) {
+            lb[c] = m;
+            atomicAdd(lbsum, m);
+        }
+    }
+}
+
+// Enumerate the component's minimal covers within its budget.  write == 0:
+// cnt[c * 64 + s] = covers of size s, tot[c] = all of them; write == 1:
+// list[loff[c] + i] = the i-th cover's mask (in the same order).
+template <typename C>
+__global__ void __launch_bounds__(64) k_en_enum(uint32_t ncomp, const uint32_t* off, const C* col,
+                                                const uint32_t* loc, const uint32_t* verts,
+                                                const uint32_t* coff, const uint32_t* lb,
+                                                const uint32_t* lbsum, int64_t k, int write,
+                                                uint64_t* cnt, uint32_t* tot, const uint32_t* loff,
+                                                uint64_t* list, uint64_t node_limit,
+                                                uint32_t* err) {
+    const uint32_t l = threadIdx.x & 63u;
+    for (uint32_t c = blockIdx.x; c < ncomp; c += gridDim.x) {
+        const uint32_t base = coff[c], nc = coff[c + 1] - base;
+        const uint64_t adj = en_adj(off, col, loc, verts, base, nc);
+        const int64_t budget = k - ((int64_t)*lbsum - (int64_t)lb[c]);
+        uint64_t mycnt = 0;  // lane s: covers of size s
+        uint32_t found = 0;
+        const uint64_t lbase = write ? (uint64_t)loff[c] : 0ull;
+        // the pending "u out" branches, one per lane (a path makes at most
+        // nc <= 64 of them)
+        uint64_t st_in = 0, st_out = 0;
+        uint32_t st_size = 0;
+        uint32_t sp = 0;
+        uint64_t in = 0, out = 0;
+        uint32_t size = 0;
+        uint64_t nodes = 0;
+        bool live = budget >= 0;
+        while (live) {
+            if (node_limit && ++nodes > node_limit) {
+                if (l == 0) atomicOr(err, 1u);
+                break;
+            }
+            const bool unc = l < nc && !((in >> l) & 1ull) && (adj & ~in) != 0ull;
+            const uint64_t m = ballot(unc);
+            bool pop = false;
+            if (m == 0ull) {
+                // every edge covered: keep C if each of its vertices has a
+                // neighbour outside it
+                const bool bad = l < nc && ((in >> l) & 1ull) && (adj & ~in) == 0ull;
+                if (ballot(bad) == 0ull) {
+                    if (write) {
+                        if (l == 0) list[lbase + found] = in;
+                    } else if (l == size) {
+                        ++mycnt;
+                    }
+                    if (++found > EN_LIST_MAX) {
+                        if (l == 0) atomicOr(err, 2u);
+                        break;
+                    }
+                }
+                pop = true;
+            } else {
+                const uint32_t u = (uint32_t)__builtin_ctzll(m);
+                const uint64_t au = rl64(adj, u);
+                if ((au & out) == 0ull) {
+                    const uint32_t sb = size + (uint32_t)__builtin_popcountll(au & ~in);
+                    if ((int64_t)sb <= budget) {
+                        if (l == sp) {
+                            st_in = in | au;
+                            st_out = out | (1ull << u);
+                            st_size = sb;
+                        }
+                        ++sp;
+                    }
+                }
+                in |= 1ull << u;
+                ++size;
+                if ((int64_t)size > budget) pop = true;
+            }
+            if (pop) {
+                if (sp == 0) break;
+                --sp;
+                in = rl64(st_in, sp);
+                out = rl64(st_out, sp);
+                size = (uint32_t)__builtin_amdgcn_readlane((int)st_size, (int)sp);
+            }
+        }
+        if (!write) {
+            cnt[(uint64_t)c * 64u + l] = mycnt;
+            if (l == 0) {
+                tot[c] = found;
+                atomicAdd(reinterpret_cast<unsigned long long*>(err + 1), (unsigned long long)found);
+            }
+        }
+    }
+}
+
+// ways[c * (k + 1) + b]: choices of one cover from each of components c..
+// with total size <= b; one wave, components from the last to the first
+__global__ void __launch_bounds__(64) k_en_ways(uint32_t ncomp, uint32_t k, const uint64_t* cnt,
+                                                uint64_t* ways) {
+    const uint32_t l = threadIdx.x;
+    const uint64_t w = (uint64_t)k + 1u;
+    for (uint32_t b = l; b <= k; b += 64) ways[(uint64_t)ncomp * w + b] = 1ull;
+    __syncthreads();
+    for (int64_t c = (int64_t)ncomp - 1; c >= 0; --c) {
+        for (uint32_t b = l; b <= k; b += 64) {
+            uint64_t sum = 0;
+            for (uint32_t s = 0; s < 64 && s <= b; ++s) {
+                const uint64_t cs = cnt[(uint64_t)c * 64u + s];
+                if (cs) sum = sat_add(sum, sat_mul(cs, ways[(uint64_t)(c + 1) * w + (b - s)]));
+            }
+            ways[(uint64_t)c * w + b] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// cover t of the combined list, for t < nout: ids ascending in out[t * k ..]
+__global__ void k_en_unrank(uint64_t nout, uint32_t ncomp, uint32_t k, const uint64_t* ways,
+                            const uint32_t* loff, const uint64_t* list, const uint32_t* coff,
+                            const uint32_t* verts, uint32_t* out, uint32_t* sizes) {
+    const uint64_t w = (uint64_t)k + 1u;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nout;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t r = t;
+        uint32_t b = k, len = 0;
+        uint32_t* o = out + t * k;
+        for (uint32_t c = 0; c < ncomp; ++c) {
+            for (uint32_t i = loff[c]; i < loff[c + 1]; ++i) {
+                const uint64_t x = list[i];
+                const uint32_t s = (uint32_t)__builtin_popcountll(x);
+                if (s > b) continue;
+                const uint64_t wc = ways[(uint64_t)(c + 1) * w + (b - s)];
+                if (r < wc) {
+                    for (uint64_t y = x; y; y &= y - 1ull) {
+                        // insertion keeps the ids ascending
+                        uint32_t v = verts[coff[c] + (uint32_t)__builtin_ctzll(y)];
+                        uint32_t p = len++;
+                        while (p > 0 && o[p - 1] > v) {
+                            o[p] = o[p - 1];
+                            --p;
+                        }
+                        o[p] = v;
+                    }
+                    b -= s;
+                    break;
+                }
+                r -= wc;
+            }
+        }
+        sizes[t] = len;
+    }
+}
+
+inline uint32_t en_grid(uint64_t n) {
+    uint64_t b = (n + 255) / 256;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b, 1), 4096);
+}
+
+template <typename C>
+vc_status enum_t(vc_ctx* c, const RootGraph& g, uint32_t k, uint64_t max_covers, uint32_t* covers,
+                 uint32_t* sizes, uint64_t* count) {
+    hipStream_t s = c->stream;
+    const uint32_t n = g.n;
+    const C* col = (const C*)g.col;
+    const uint32_t grid = en_grid(n);
+    DevBuf* B = c->en;
+    // ctr: 0 changed, 1 max component size, 2 sum of lb, 3 error bits,
+    // 4-5 covers of all components (64-bit)
+    HIPCHK(ensure(B[0], 64));
+    uint32_t* ctr = (uint32_t*)B[0].p;
+    HIPCHK(ensure(B[1], 4ull * n));        // label
+    HIPCHK(ensure(B[2], 4ull * (n + 1)));  // root flags, then component sizes
+    HIPCHK(ensure(B[3], 4ull * (n + 1)));  // rank of each root
+    HIPCHK(ensure(B[4], 4ull * n));        // local ids
+    HIPCHK(ensure(B[5], 4ull * n));        // vertices by component
+    HIPCHK(ensure(B[6], 4ull * (n / 2048 + 4)));  // scan scratch
+    uint32_t *label = (uint32_t*)B[1].p, *flag = (uint32_t*)B[2].p, *rank = (uint32_t*)B[3].p;
+    uint32_t *loc = (uint32_t*)B[4].p, *verts = (uint32_t*)B[5].p, *tmp = (uint32_t*)B[6].p;
+    HIPCHK(hipMemsetAsync(ctr, 0, 64, s));
+    hipLaunchKernelGGL(k_en_label_init, dim3(grid), dim3(256), 0, s, n, g.off, label);
+    for (uint32_t it = 0;; it += 8) {
+        HIPCHK(hipMemsetAsync(ctr, 0, 4, s));
+        for (uint32_t j = 0; j < 8; ++j)
+            hipLaunchKernelGGL(k_en_label_prop<C>, dim3(grid), dim3(256), 0, s, n, g.off, col,
+                               label, ctr);
+        HIPCHK(hipGetLastError());
+        uint32_t ch = 0;
+        HIPCHK(hipMemcpyAsync(&ch, ctr, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (ch == 0) break;
+        if (it > n + 8u) return VC_EDEVICE;  // labels only decrease
+    }
+    hipLaunchKernelGGL(k_en_roots, dim3(grid), dim3(256), 0, s, n, label, flag);
+    HIPCHK(scan_u32(flag, n, rank, tmp, s));
+    uint32_t ncomp = 0;
+    HIPCHK(hipMemcpyAsync(&ncomp, rank + n, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ncomp == 0) return VC_EDEVICE;  // an edge makes a component
+    uint32_t* csize = flag;  // roots are ranked: reuse the flags as sizes
+    HIPCHK(hipMemsetAsync(csize, 0, 4ull * (ncomp + 1), s));
+    hipLaunchKernelGGL(k_en_local, dim3(grid), dim3(256), 0, s, n, label, rank, loc, csize,
+                       ctr + 1);
+    uint32_t maxsize = 0;
+    HIPCHK(hipMemcpyAsync(&maxsize, ctr + 1, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (maxsize > EN_MAXC) return VC_ERANGE;
+    HIPCHK(ensure(B[7], 4ull * (ncomp + 1)));  // component offsets
+    uint32_t* coff = (uint32_t*)B[7].p;
+    HIPCHK(scan_u32(csize, ncomp, coff, tmp, s));
+    hipLaunchKernelGGL(k_en_place, dim3(grid), dim3(256), 0, s, n, label, rank, loc, coff, verts);
+    // lower bounds, then counts by size
+    HIPCHK(ensure(B[8], 4ull * ncomp + 4ull * (ncomp + 1)));  // lb, totals
+    uint32_t* lb = (uint32_t*)B[8].p;
+    uint32_t* tot = lb + ncomp;
+    HIPCHK(ensure(B[9], 8ull * 64u * ncomp));
+    uint64_t* cnt = (uint64_t*)B[9].p;
+    const uint32_t cgrid = std::min<uint32_t>(ncomp, 65535u);
+    hipLaunchKernelGGL(k_en_lb<C>, dim3(cgrid), dim3(64), 0, s, ncomp, g.off, col, loc, verts,
+                       coff, lb, ctr + 2);
+    const uint64_t nl = c->opts.node_limit;
+    hipLaunchKernelGGL(k_en_enum<C>, dim3(cgrid), dim3(64), 0, s, ncomp, g.off, col, loc, verts,
+                       coff, lb, ctr + 2, (int64_t)k, 0, cnt, tot, (const uint32_t*)nullptr,
+                       (uint64_t*)nullptr, nl, ctr + 3);
+    HIPCHK(hipGetLastError());
+    // list offsets (the component lists stay below 2^26 entries in all)
+    HIPCHK(ensure(B[10], 4ull * (ncomp + 1)));
+    uint32_t* loff = (uint32_t*)B[10].p;
+    HIPCHK(scan_u32(tot, ncomp, loff, tmp, s));
+    uint32_t hdr[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(&hdr[0], ctr + 3, 12, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hdr[0] & 1u) return VC_ETIMEDOUT;
+    const uint64_t nlist = (uint64_t)hdr[1] | ((uint64_t)hdr[2] << 32);
+    if ((hdr[0] & 2u) || nlist > EN_LIST_MAX) return VC_ERANGE;
+    const uint64_t wsz = ((uint64_t)ncomp + 1u) * ((uint64_t)k + 1u);
+    if (wsz > EN_WAYS_MAX) return VC_ERANGE;
+    HIPCHK(ensure(B[11], 8ull * (nlist ? nlist : 1) + 8ull * wsz));
+    uint64_t* list = (uint64_t*)B[11].p;
+    uint64_t* ways = list + (nlist ? nlist : 1);
+    if (nlist)
+        hipLaunchKernelGGL(k_en_enum<C>, dim3(cgrid), dim3(64), 0, s, ncomp, g.off, col, loc,
+                           verts, coff, lb, ctr + 2, (int64_t)k, 1, cnt, tot, loff, list, nl,
+                           ctr + 3);
+    hipLaunchKernelGGL(k_en_ways, dim3(1), dim3(64), 0, s, ncomp, k, cnt, ways);
+    HIPCHK(hipGetLastError());
+    uint64_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, ways + k, 8, hipMemcpyDeviceToHost, s));  // ways[0][k]
+    HIPCHK(hipStreamSynchronize(s));
+    *count = total;
+    const uint64_t nout = std::min<uint64_t>(total, max_covers);
+    if (nout && k) {
+        HIPCHK(ensure(B[12], 4ull * nout * k + 4ull * nout));
+        uint32_t* dout = (uint32_t*)B[12].p;
+        uint32_t* dsz = dout + nout * k;
+        hipLaunchKernelGGL(k_en_unrank, dim3(en_grid(nout)), dim3(256), 0, s, nout, ncomp, k, ways,
+                           loff, list, coff, verts, dout, dsz);
+        HIPCHK(hipGetLastError());
+        if (covers) HIPCHK(hipMemcpyAsync(covers, dout, 4ull * nout * k, hipMemcpyDeviceToHost, s));
+        if (sizes) HIPCHK(hipMemcpyAsync(sizes, dsz, 4ull * nout, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } else if (nout && sizes) {
+        memset(sizes, 0, 4ull * nout);  // k = 0: the only cover is empty
+    }
+    return VC_OK;
+}
+
+}  // namespace
+
+}  // namespace vc
+
+extern "C" vc_status vc_param_enum(vc_ctx* c, const vc_csr* g, uint32_t k, uint64_t max_covers,
+                                   uint32_t* covers, uint32_t* sizes, uint64_t* count) {
+    if (!c || !g || !count) return VC_EINVAL;
+    if (max_covers && ((k && !covers) || !sizes)) return VC_EINVAL;
+    if (vc::server_busy(c)) return VC_EAGAIN;
+    if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    vc::RootGraph rg;
+    vc_status st = vc::stage_input(c, g, &rg);
+    if (st) return st;
+    if (g->n == 0 || g->nnz == 0) {
+        // no edge: the empty set is the one minimal cover
+        *count = 1;
+        if (max_covers && sizes) sizes[0] = 0;
+        return VC_OK;
+    }
+    uint64_t cnt = 0;
+    st = g->col_bytes == 2
+             ? vc::enum_t<uint16_t>(c, rg, k, max_covers, covers, sizes, &cnt)
+             : vc::enum_t<uint32_t>(c, rg, k, max_covers, covers, sizes, &cnt);
+    if (st) return st;
+    *count = cnt;
+    return VC_OK;
+}

@@ -35,7 +35,7 @@ CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]
 
 EXPORTS = ["vc_ctx_create", "vc_ctx_destroy", "vc_validate", "vc_min",
            "vc_param", "vc_min_batch", "vc_param_batch", "vc_submit", "vc_poll",
-           "vc_cancel", "vc_last_stats", "vc_status_str"]
+           "vc_cancel", "vc_last_stats", "vc_status_str", "vc_param_enum"]
 
 
 class vc_csr(ctypes.Structure):
@@ -144,6 +144,9 @@ def load():
     lib.vc_cancel.argtypes = [p, ctypes.c_uint64]
     lib.vc_last_stats.restype = ctypes.c_int
     lib.vc_last_stats.argtypes = [p, ctypes.POINTER(vc_stats)]
+    lib.vc_param_enum.restype = ctypes.c_int
+    lib.vc_param_enum.argtypes = [p, ctypes.POINTER(vc_csr), ctypes.c_uint32, ctypes.c_uint64,
+                                  u32p, u32p, u64p]
     lib.vc_status_str.restype = ctypes.c_char_p
     lib.vc_status_str.argtypes = [ctypes.c_int]
     _lib = lib
@@ -343,6 +346,23 @@ class Solver:
                              cp, ctypes.byref(clen))
         _check(st, "vc_param")
         return Result(None, bool(yes.value), cov[:clen.value].copy(), self.stats())
+
+    def enum_minimal(self, g, k: int, max_covers: int = 100_000):
+        """vc_param_enum: (count, list of the first min(count, max_covers)
+        minimal covers of size <= k, each an ascending id array)."""
+        c, keep = self._csr(g)
+        kk = int(k)
+        covers = np.zeros(max(max_covers * kk, 1), np.uint32)
+        sizes = np.zeros(max(max_covers, 1), np.uint32)
+        cnt = ctypes.c_uint64(0)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        st = load().vc_param_enum(self._h, ctypes.byref(c), kk, int(max_covers),
+                                  covers.ctypes.data_as(u32p), sizes.ctypes.data_as(u32p),
+                                  ctypes.byref(cnt))
+        _check(st, "vc_param_enum")
+        got = min(int(cnt.value), int(max_covers))
+        out = [covers[t * kk:t * kk + int(sizes[t])].copy() for t in range(got)]
+        return int(cnt.value), out
 
 
     def submit(self, g, kind: int = VC_MIN, k: int = 0) -> int:
