@@ -18,6 +18,10 @@ arrivals; p50/p99 latency and solves/s, against the plain solver serving
 the same arrivals first come first served.
 --workload ablation: each optimization switched off in turn (Table II) on
 the blocks-and-hubs graph and on 20 G(60, 0.1) graphs.
+--workload enum: enumeration of the minimal covers of size <= MVC + 1 on 20
+G(60, 0.1) graphs (the enumeration variant of PVC).
+--workload pvc_powerlaw: the two PVC queries (k = MVC - 1, MVC) on the
+planted power-law graph with 10^6 vertices and 5*10^6 edges.
 
 Prints one JSON line.  Only one GPU is supported: --gpus N with N > 1 exits.
 """
@@ -369,12 +373,116 @@ def bench_ablation(args, torch, gg, vc):
     }
 
 
+def bench_pvc_powerlaw(args, torch, gg, vc):
+    """PVC on the planted power-law graph (n = 10^6, m = 5*10^6, gamma 2.1,
+    |S| = 60,000; CSR uint32 resident in HBM): one step is the two queries
+    k = MVC - 1 (no) and k = MVC (yes, with a cover), MVC taken from vc_min
+    on the same graph; each call runs to solution (validation, greedy bound,
+    root reduction, induce, search if anything is left, cover)."""
+    import numpy as np
+    g = gg.config3_chung_lu()
+    dg = vc.DeviceGraph.from_graph(g, "cuda:0")
+    torch.cuda.synchronize()
+    solver = vc.Solver(0, watchdog_ms=120_000)
+    m = solver.mvc(dg).size
+    for _ in range(args.warmup):
+        solver.pvc(dg, m - 1)
+        solver.pvc(dg, m)
+    torch.cuda.synchronize()
+    t_no, t_yes, st = [], [], None
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        no = solver.pvc(dg, m - 1)
+        t1 = time.perf_counter()
+        yes = solver.pvc(dg, m)
+        t2 = time.perf_counter()
+        assert not no.yes and yes.yes and yes.cover.size <= m
+        t_no.append(t1 - t0)
+        t_yes.append(t2 - t1)
+        st = yes.stats
+    t0 = time.perf_counter()
+    r = solver.mvc(dg)
+    t_mvc = time.perf_counter() - t0
+    solver.close()
+    el = sum(t_no) + sum(t_yes)
+    out = {
+        "metric": METRIC, "value": 2 * args.steps / el, "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "pvc_chung_lu_n1e6_m5e6", "n": g.n, "m": g.m, "mvc": m,
+                   "ms_k_mvc_minus_1": float(np.median(t_no)) * 1e3,
+                   "ms_k_mvc": float(np.median(t_yes)) * 1e3, "ms_mvc": t_mvc * 1e3,
+                   "greedy_size": st["greedy_size"], "forced_root": st["forced_root"],
+                   "n_kernel": st["n_kernel"], "root_rounds": st["root_rounds"],
+                   "ms_root_device": st["ms_root"]},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        o1 = oracle.pvc(g, m - 1)
+        o2 = oracle.pvc(g, m)
+        dt = time.perf_counter() - t0
+        assert not o1["yes"] and o2["yes"]
+        out["cpu_baseline"] = {"value": 2 / dt, "unit": "queries/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the same two queries ({dt:.2f} s)"}
+    return out
+
+
+def bench_enum(args, torch, gg, vc):
+    """Enumeration of the minimal vertex covers of size <= MVC + 1 on 20
+    G(60, 0.1) graphs (vc_param_enum; k from vc_min on the same graph), with
+    the oracle's enumeration timed beside it on the same graphs."""
+    graphs = [gg.config1_gnp60(s) for s in range(1, 21)]
+    dev = [vc.DeviceGraph.from_graph(g, "cuda:0") for g in graphs]
+    torch.cuda.synchronize()
+    solver = vc.Solver(0, watchdog_ms=120_000)
+    ks = [solver.mvc(d, want_cover=False).size + 1 for d in dev]
+    for _ in range(args.warmup):
+        for d, k in zip(dev, ks):
+            solver.enum_minimal(d, k, 4096)
+    torch.cuda.synchronize()
+    covers = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        covers = 0
+        for d, k in zip(dev, ks):
+            covers += solver.enum_minimal(d, k, 4096)[0]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    solver.close()
+    out = {
+        "metric": METRIC, "value": len(graphs) * args.steps / el, "unit": "graphs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "enum_minimal_gnp60_x20_k_mvc_plus_1",
+                   "minimal_covers_per_step": covers,
+                   "covers_per_s": covers * args.steps / el},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        done, ocov = 0, 0
+        while done < len(graphs) and time.perf_counter() - t0 < args.cpu_seconds:
+            ocov += oracle.enum_minimal(graphs[done], ks[done])["count"]
+            done += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done / dt, "unit": "graphs/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{done} of the 20 graphs enumerated ({dt:.1f} s, "
+                                         f"{ocov} minimal covers)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["blocks_hubs", "batch", "serve", "ablation"],
+    ap.add_argument("--workload", choices=["blocks_hubs", "batch", "serve", "ablation", "enum",
+                             "pvc_powerlaw"],
                     default="blocks_hubs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -405,7 +513,8 @@ def main():
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     fn = {"blocks_hubs": bench_blocks_hubs, "batch": bench_batch, "serve": bench_serve,
-          "ablation": bench_ablation}
+          "ablation": bench_ablation, "enum": bench_enum,
+          "pvc_powerlaw": bench_pvc_powerlaw}
     out = fn[args.workload](args, torch, gg, vc)
     print(json.dumps(out), flush=True)
 

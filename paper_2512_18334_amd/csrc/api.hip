@@ -219,12 +219,26 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     HIPCHK(hipMemsetAsync(b.ctr, 0, CTR_COUNT * 4, s));
     HIPCHK(hipEventRecord(c->ev[0], s));
     HIPCHK(root_init(rg, b, s));
+    // The degree rules need no bound: they run first, and the greedy bound
+    // (Sec. II-B) is taken on what they leave, starting from the vertices
+    // they forced (an attained cover either way; on graphs the rules settle,
+    // no greedy round is left to run).  VC_OPT_NO_INDUCE skips all root rules.
+    const bool no_induce = (c->opts.flags & VC_OPT_NO_INDUCE) != 0;
+    uint32_t rounds = 0;
+    if (!no_induce) {
+        HIPCHK(root_reduce(rg, b, 0x3FFFFFFF, s, 1u << 16, &rounds));
+        HIPCHK(root_greedy_rest(rg, b, s));
+    }
     uint32_t grounds = 0;
     HIPCHK(root_greedy(rg, b, s, &grounds));
-    uint32_t gsize = 0;
-    HIPCHK(hipMemcpyAsync(&gsize, b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, s));
+    uint32_t ghdr[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&ghdr[0], b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&ghdr[1], b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    const uint32_t gsize = ghdr[0] + ghdr[1];  // forced + greedy
     stv.greedy_size = gsize;
+    stv.root_rounds = rounds;
+    stv.forced_root = ghdr[1];
 
     auto finish_with_greedy = [&](int yes) -> vc_status {
         // the greedy cover is the answer (MVC), or a PVC yes within k
@@ -261,9 +275,11 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
 
     // root reduction to a fixpoint under the bound best0 (Sec. IV-B)
     // (skipped under VC_OPT_NO_INDUCE: the search starts from the input)
-    const bool no_induce = (c->opts.flags & VC_OPT_NO_INDUCE) != 0;
-    uint32_t rounds = 0;
-    if (!no_induce) HIPCHK(root_reduce(rg, b, best0, s, 1u << 16, &rounds));
+    if (!no_induce) {
+        uint32_t r2 = 0;
+        HIPCHK(root_reduce(rg, b, best0, s, 1u << 16, &r2));
+        rounds += r2;
+    }
     stv.root_rounds = rounds;
     uint32_t sroot = 0;
     HIPCHK(hipMemcpyAsync(&sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));

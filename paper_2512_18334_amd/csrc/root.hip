@@ -196,6 +196,16 @@ __global__ void k_greedy_apply(uint32_t n, const uint32_t* off, const C* col, ui
     wave_atomic_add(ctr_size, taken);
 }
 
+// the greedy restarted on what the root rules left: working degrees of the
+// live vertices only, and the vertices the rules forced already in its cover
+__global__ void k_greedy_rest(uint32_t n, const uint32_t* rdeg, uint32_t* gdeg, uint8_t* gin) {
+    GRID_LOOP(v, n) {
+        const uint32_t d = rdeg[v];
+        gdeg[v] = rlive(d) ? d : 0u;
+        gin[v] = d == RIN ? 1 : 0;
+    }
+}
+
 // ------------------------------------------------------------- root reduce
 // One round = decide (rules on the state before the round, with the same
 // tie-breaks as the search kernel), mark (flags -> in the cover), remove
@@ -530,6 +540,12 @@ static hipError_t greedy_t(const RootGraph& g, const RootBufs& b, hipStream_t st
             return hipSuccess;
         }
     }
+}
+
+hipError_t root_greedy_rest(const RootGraph& g, const RootBufs& b, hipStream_t st) {
+    hipLaunchKernelGGL(k_greedy_rest, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, b.rdeg, b.gdeg,
+                       b.gin);
+    return hipGetLastError();
 }
 
 hipError_t root_greedy(const RootGraph& g, const RootBufs& b, hipStream_t st, uint32_t* rounds) {

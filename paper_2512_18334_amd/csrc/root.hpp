@@ -53,6 +53,9 @@ hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* 
                          hipStream_t st, uint32_t* bad_host);
 hipError_t root_init(const RootGraph& g, const RootBufs& b, hipStream_t st);
 hipError_t root_greedy(const RootGraph& g, const RootBufs& b, hipStream_t st, uint32_t* rounds);
+// restart the greedy on the vertices the root rules left (gdeg from rdeg,
+// the forced vertices already in the greedy cover)
+hipError_t root_greedy_rest(const RootGraph& g, const RootBufs& b, hipStream_t st);
 hipError_t root_reduce(const RootGraph& g, const RootBufs& b, int best0, hipStream_t st,
                        uint32_t max_rounds, uint32_t* rounds);
 // keep_all: every input vertex keeps its id (isolated ones with degree 0)
