@@ -385,10 +385,18 @@ vc_status Server::start(Req& r) {
         HIPCHK(hipGetLastError());
     }
     HIPCHK(root_init(rg, b, ss));
+    // the degree rules first (they need no bound), then the greedy bound on
+    // what they leave, starting from the vertices they forced
+    uint32_t rounds0 = 0;
+    HIPCHK(root_reduce(rg, b, 0x3FFFFFFF, ss, 1u << 16, &rounds0));
+    HIPCHK(root_greedy_rest(rg, b, ss));
     uint32_t grounds = 0;
     HIPCHK(root_greedy(rg, b, ss, &grounds));
-    HIPCHK(hipMemcpyAsync(&r.gsize, b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, ss));
+    uint32_t ghdr[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&ghdr[0], b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, ss));
+    HIPCHK(hipMemcpyAsync(&ghdr[1], b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, ss));
     HIPCHK(hipStreamSynchronize(ss));
+    r.gsize = ghdr[0] + ghdr[1];  // forced + greedy
     auto list_to_host = [&](int improved, uint32_t np_, const uint32_t* bm) -> vc_status {
         HIPCHK(root_cover(rg, b, np_, improved, bm, ss));
         uint32_t cnt = 0;
