@@ -156,91 +156,136 @@ __global__ void __launch_bounds__(64) k_en_lb(uint32_t ncomp, const uint32_t* of
     }
 }
 
-// Enumerate the component's minimal covers within its budget.  write == 0:
-// cnt[c * 64 + s] = covers of size s, tot[c] = all of them; write == 1:
-// list[loff[c] + i] = the i-th cover's mask (in the same order).
+// Enumerate the component's minimal covers within its budget, split over
+// 2^L threads per component (L <= 22): thread j replays the first L branch
+// decisions from the bits of j (bit d: 0 = u in, 1 = u out and N(u) in), then walks
+// the subtree below with a private stack.  A path that ends above depth L
+// (a leaf, a cut or a dropped branch) belongs to the one j whose remaining
+// bits are zero, so nothing is counted twice.  write == 0: cnt[c * 64 + s]
+// counts the covers of size s; write == 1: each cover's mask goes to
+// list[loff[c] + cur[c]++].
+__device__ __forceinline__ uint32_t en_first_uncovered(const uint64_t* adj, uint64_t in,
+                                                       uint64_t full) {
+    for (uint64_t cand = ~in & full; cand; cand &= cand - 1ull) {
+        const uint32_t v = (uint32_t)__builtin_ctzll(cand);
+        if (adj[v] & ~in) return v;
+    }
+    return EN_NONE;
+}
+
+__device__ __forceinline__ bool en_minimal(const uint64_t* adj, uint64_t in) {
+    for (uint64_t x = in; x; x &= x - 1ull)
+        if ((adj[__builtin_ctzll(x)] & ~in) == 0ull) return false;
+    return true;
+}
+
 template <typename C>
-__global__ void __launch_bounds__(64) k_en_enum(uint32_t ncomp, const uint32_t* off, const C* col,
-                                                const uint32_t* loc, const uint32_t* verts,
-                                                const uint32_t* coff, const uint32_t* lb,
-                                                const uint32_t* lbsum, int64_t k, int write,
-                                                uint64_t* cnt, uint32_t* tot, const uint32_t* loff,
-                                                uint64_t* list, uint64_t node_limit,
-                                                uint32_t* err) {
-    const uint32_t l = threadIdx.x & 63u;
-    for (uint32_t c = blockIdx.x; c < ncomp; c += gridDim.x) {
-        const uint32_t base = coff[c], nc = coff[c + 1] - base;
-        const uint64_t adj = en_adj(off, col, loc, verts, base, nc);
-        const int64_t budget = k - ((int64_t)*lbsum - (int64_t)lb[c]);
-        uint64_t mycnt = 0;  // lane s: covers of size s
-        uint32_t found = 0;
-        const uint64_t lbase = write ? (uint64_t)loff[c] : 0ull;
-        // the pending "u out" branches, one per lane (a path makes at most
-        // nc <= 64 of them)
-        uint64_t st_in = 0, st_out = 0;
-        uint32_t st_size = 0;
-        uint32_t sp = 0;
-        uint64_t in = 0, out = 0;
-        uint32_t size = 0;
-        uint64_t nodes = 0;
-        bool live = budget >= 0;
-        while (live) {
-            if (node_limit && ++nodes > node_limit) {
-                if (l == 0) atomicOr(err, 1u);
-                break;
-            }
-            const bool unc = l < nc && !((in >> l) & 1ull) && (adj & ~in) != 0ull;
-            const uint64_t m = ballot(unc);
-            bool pop = false;
-            if (m == 0ull) {
-                // every edge covered: keep C if each of its vertices has a
-                // neighbour outside it
-                const bool bad = l < nc && ((in >> l) & 1ull) && (adj & ~in) == 0ull;
-                if (ballot(bad) == 0ull) {
-                    if (write) {
-                        if (l == 0) list[lbase + found] = in;
-                    } else if (l == size) {
-                        ++mycnt;
-                    }
-                    if (++found > EN_LIST_MAX) {
-                        if (l == 0) atomicOr(err, 2u);
-                        break;
-                    }
-                }
-                pop = true;
-            } else {
-                const uint32_t u = (uint32_t)__builtin_ctzll(m);
-                const uint64_t au = rl64(adj, u);
-                if ((au & out) == 0ull) {
-                    const uint32_t sb = size + (uint32_t)__builtin_popcountll(au & ~in);
-                    if ((int64_t)sb <= budget) {
-                        if (l == sp) {
-                            st_in = in | au;
-                            st_out = out | (1ull << u);
-                            st_size = sb;
-                        }
-                        ++sp;
-                    }
-                }
-                in |= 1ull << u;
-                ++size;
-                if ((int64_t)size > budget) pop = true;
-            }
-            if (pop) {
-                if (sp == 0) break;
-                --sp;
-                in = rl64(st_in, sp);
-                out = rl64(st_out, sp);
-                size = (uint32_t)__builtin_amdgcn_readlane((int)st_size, (int)sp);
-            }
+__global__ void __launch_bounds__(256) k_en_enum(uint32_t ncomp, uint32_t L, const uint32_t* off,
+                                                 const C* col, const uint32_t* loc,
+                                                 const uint32_t* verts, const uint32_t* coff,
+                                                 const uint32_t* lb, const uint32_t* lbsum,
+                                                 int64_t k, int write, unsigned long long* cnt,
+                                                 uint32_t* cur, const uint32_t* loff,
+                                                 uint64_t* list, uint64_t node_limit,
+                                                 uint32_t* err) {
+    __shared__ uint64_t adj[EN_MAXC];
+    const uint32_t per = (1u << L) > 256u ? (1u << L) / 256u : 1u;  // blocks per component
+    const uint32_t c = blockIdx.x / per;
+    if (c >= ncomp) return;
+    const uint32_t base = coff[c], nc = coff[c + 1] - base;
+    if (threadIdx.x < EN_MAXC) {
+        uint64_t a = 0;
+        if (threadIdx.x < nc) {
+            const uint32_t v = verts[base + threadIdx.x];
+            for (uint32_t e = off[v]; e < off[v + 1]; ++e) a |= 1ull << loc[(uint32_t)col[e]];
         }
-        if (!write) {
-            cnt[(uint64_t)c * 64u + l] = mycnt;
-            if (l == 0) {
-                tot[c] = found;
-                atomicAdd(reinterpret_cast<unsigned long long*>(err + 1), (unsigned long long)found);
-            }
+        adj[threadIdx.x] = a;
+    }
+    __syncthreads();
+    const uint32_t j = (blockIdx.x % per) * 256u + threadIdx.x;
+    if (j >= (1u << L)) return;
+    const int64_t budget = k - ((int64_t)*lbsum - (int64_t)lb[c]);
+    if (budget < 0) return;
+    const uint64_t full = nc >= 64u ? ~0ull : ((1ull << nc) - 1ull);
+    auto emit = [&](uint64_t in, uint32_t size) {
+        if (write) {
+            const uint32_t pos = atomicAdd(&cur[c], 1u);
+            list[(uint64_t)loff[c] + pos] = in;
+        } else {
+            atomicAdd(&cnt[(uint64_t)c * 64u + size], 1ull);
         }
+    };
+    uint64_t in = 0, out = 0;
+    uint32_t size = 0;
+    // the prefix
+    for (uint32_t d = 0; d < L; ++d) {
+        const uint32_t u = en_first_uncovered(adj, in, full);
+        if (u == EN_NONE) {
+            if ((j >> d) == 0u && en_minimal(adj, in)) emit(in, size);
+            return;
+        }
+        if (((j >> d) & 1u) == 0u) {
+            in |= 1ull << u;
+            ++size;
+            if ((int64_t)size > budget) return;
+        } else {
+            const uint64_t au = adj[u];
+            if (au & out) return;
+            size += (uint32_t)__builtin_popcountll(au & ~in);
+            if ((int64_t)size > budget) return;
+            in |= au;
+            out |= 1ull << u;
+        }
+    }
+    // the subtree below, depth first (a path holds at most nc pending
+    // "u out" branches, one per vertex put in the cover on it)
+    uint64_t st_in[EN_MAXC], st_out[EN_MAXC];
+    uint32_t st_size[EN_MAXC];
+    uint32_t sp = 0;
+    uint64_t nodes = 0;
+    for (;;) {
+        if (node_limit && ++nodes > node_limit) {
+            atomicOr(err, 1u);
+            return;
+        }
+        const uint32_t u = en_first_uncovered(adj, in, full);
+        bool pop = false;
+        if (u == EN_NONE) {
+            if (en_minimal(adj, in)) emit(in, size);
+            pop = true;
+        } else {
+            const uint64_t au = adj[u];
+            if ((au & out) == 0ull) {
+                const uint32_t sb = size + (uint32_t)__builtin_popcountll(au & ~in);
+                if ((int64_t)sb <= budget && sp < EN_MAXC) {
+                    st_in[sp] = in | au;
+                    st_out[sp] = out | (1ull << u);
+                    st_size[sp] = sb;
+                    ++sp;
+                }
+            }
+            in |= 1ull << u;
+            ++size;
+            if ((int64_t)size > budget) pop = true;
+        }
+        if (pop) {
+            if (sp == 0) return;
+            --sp;
+            in = st_in[sp];
+            out = st_out[sp];
+            size = st_size[sp];
+        }
+    }
+}
+
+// per component: its number of covers (the list length) and the total
+__global__ void k_en_tot(uint32_t ncomp, const unsigned long long* cnt, uint32_t* tot,
+                         unsigned long long* all) {
+    EN_GRID_LOOP(c, ncomp) {
+        unsigned long long t = 0;
+        for (uint32_t s = 0; s < 64; ++s) t += cnt[(uint64_t)c * 64u + s];
+        tot[c] = t > EN_LIST_MAX ? (uint32_t)(EN_LIST_MAX + 1u) : (uint32_t)t;
+        atomicAdd(all, t);
     }
 }
 
@@ -369,9 +414,22 @@ vc_status enum_t(vc_ctx* c, const RootGraph& g, uint32_t k, uint64_t max_covers,
     hipLaunchKernelGGL(k_en_lb<C>, dim3(cgrid), dim3(64), 0, s, ncomp, g.off, col, loc, verts,
                        coff, lb, ctr + 2);
     const uint64_t nl = c->opts.node_limit;
-    hipLaunchKernelGGL(k_en_enum<C>, dim3(cgrid), dim3(64), 0, s, ncomp, g.off, col, loc, verts,
-                       coff, lb, ctr + 2, (int64_t)k, 0, cnt, tot, (const uint32_t*)nullptr,
+    // 2^L threads per component, about 2^24 threads in all: most prefixes
+    // end early (cut or dropped), and the deeper the split, the more evenly
+    // the surviving subtrees spread over the threads
+    uint32_t L = 4;
+    while (L < 22 && ((uint64_t)ncomp << (L + 1)) <= (1ull << 24)) ++L;
+    const uint32_t per = (1u << L) > 256u ? (1u << L) / 256u : 1u;
+    const uint64_t eblocks = (uint64_t)ncomp * per;
+    if (eblocks > 0x7FFFFFFFull) return VC_ERANGE;
+    HIPCHK(hipMemsetAsync(cnt, 0, 8ull * 64u * ncomp, s));
+    hipLaunchKernelGGL(k_en_enum<C>, dim3((uint32_t)eblocks), dim3(256), 0, s, ncomp, L, g.off, col,
+                       loc, verts, coff, lb, ctr + 2, (int64_t)k, 0,
+                       (unsigned long long*)cnt, (uint32_t*)nullptr, (const uint32_t*)nullptr,
                        (uint64_t*)nullptr, nl, ctr + 3);
+    hipLaunchKernelGGL(k_en_tot, dim3(en_grid(ncomp)), dim3(256), 0, s, ncomp,
+                       (const unsigned long long*)cnt, tot,
+                       reinterpret_cast<unsigned long long*>(ctr + 4));
     HIPCHK(hipGetLastError());
     // list offsets (the component lists stay below 2^26 entries in all)
     HIPCHK(ensure(B[10], 4ull * (ncomp + 1)));
@@ -388,10 +446,13 @@ vc_status enum_t(vc_ctx* c, const RootGraph& g, uint32_t k, uint64_t max_covers,
     HIPCHK(ensure(B[11], 8ull * (nlist ? nlist : 1) + 8ull * wsz));
     uint64_t* list = (uint64_t*)B[11].p;
     uint64_t* ways = list + (nlist ? nlist : 1);
-    if (nlist)
-        hipLaunchKernelGGL(k_en_enum<C>, dim3(cgrid), dim3(64), 0, s, ncomp, g.off, col, loc,
-                           verts, coff, lb, ctr + 2, (int64_t)k, 1, cnt, tot, loff, list, nl,
-                           ctr + 3);
+    if (nlist) {
+        uint32_t* cur = tot;  // the totals are in loff now: reuse as cursors
+        HIPCHK(hipMemsetAsync(cur, 0, 4ull * ncomp, s));
+        hipLaunchKernelGGL(k_en_enum<C>, dim3((uint32_t)eblocks), dim3(256), 0, s, ncomp, L, g.off,
+                           col, loc, verts, coff, lb, ctr + 2, (int64_t)k, 1,
+                           (unsigned long long*)cnt, cur, loff, list, nl, ctr + 3);
+    }
     hipLaunchKernelGGL(k_en_ways, dim3(1), dim3(64), 0, s, ncomp, k, cnt, ways);
     HIPCHK(hipGetLastError());
     uint64_t total = 0;
