@@ -30,6 +30,20 @@ __device__ __forceinline__ void wave_atomic_add(uint32_t* p, uint32_t x) {
     if ((threadIdx.x & 63u) == 0 && x) atomicAdd(p, x);
 }
 
+// one atomic per 256-thread block: in a round where most vertices change,
+// one atomic per wave on a single counter serialises (16K of them for a
+// million vertices); every thread of the block must call it
+__device__ __forceinline__ void block_atomic_add(uint32_t* p, uint32_t x) {
+    __shared__ uint32_t part[4];
+    x = wave_sum(x);
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(p, t);
+    }
+}
+
 #define GRID_LOOP(i, n)                                                        \
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (n);          \
          i += gridDim.x * blockDim.x)
@@ -260,7 +274,7 @@ __global__ void k_reduce_decide(uint32_t n, const uint32_t* off, const C* col,
             }
         }
     }
-    wave_atomic_add(&ctr[CTR_FIRED + (round & 1u)], fired);
+    block_atomic_add(&ctr[CTR_FIRED + (round & 1u)], fired);
 }
 
 __global__ void k_reduce_mark(uint32_t n, uint32_t* rdeg, uint8_t* addf, uint8_t* newly,
@@ -277,7 +291,7 @@ __global__ void k_reduce_mark(uint32_t n, uint32_t* rdeg, uint8_t* addf, uint8_t
             ++added;
         }
     }
-    wave_atomic_add(&ctr[CTR_SROOT], added);
+    block_atomic_add(&ctr[CTR_SROOT], added);
 }
 
 template <typename C>
