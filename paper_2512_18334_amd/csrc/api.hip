@@ -100,13 +100,14 @@ namespace {
 // this many vertices (smaller kernels are cheaper to search than to match)
 constexpr uint32_t CROWN_AUTO_MIN = 4096;
 
-vc_status device_validate(vc_ctx* c, const RootGraph& rg) {
+vc_status device_validate(vc_ctx* c, const RootGraph& rg, int* sorted = nullptr) {
     HIPCHK(ensure(c->ctr, CTR_COUNT * 4));
     HIPCHK(ensure(c->hsum, 8));
     HIPCHK(hipMemsetAsync(c->ctr.p, 0, CTR_COUNT * 4, c->stream));
     HIPCHK(hipMemsetAsync(c->hsum.p, 0, 8, c->stream));
     uint32_t bad = 0;
-    HIPCHK(root_validate(rg, (uint32_t*)c->ctr.p, (unsigned long long*)c->hsum.p, c->stream, &bad));
+    HIPCHK(root_validate(rg, (uint32_t*)c->ctr.p, (unsigned long long*)c->hsum.p, c->stream, &bad,
+                         sorted));
     return bad ? VC_EINVAL : VC_OK;
 }
 
@@ -122,7 +123,7 @@ vc_status stage_graph(vc_ctx* c, const vc_csr* g, RootGraph* rg) {
         rg->off = g->offsets;
         rg->col = g->cols;
         if (!skip && g->n) {
-            st = device_validate(c, *rg);
+            st = device_validate(c, *rg, &rg->sorted);
             if (st) return st;
         }
         return VC_OK;
@@ -130,6 +131,20 @@ vc_status stage_graph(vc_ctx* c, const vc_csr* g, RootGraph* rg) {
     if (!skip) {
         st = validate_host(g);
         if (st) return st;
+        // strictly increasing rows let the root rules bisect rows
+        int inc = 1;
+        for (uint32_t v = 0; v < g->n && inc; ++v)
+            for (uint32_t e = g->offsets[v] + 1; e < g->offsets[v + 1]; ++e) {
+                const uint32_t a = g->col_bytes == 2 ? ((const uint16_t*)g->cols)[e - 1]
+                                                     : ((const uint32_t*)g->cols)[e - 1];
+                const uint32_t b = g->col_bytes == 2 ? ((const uint16_t*)g->cols)[e]
+                                                     : ((const uint32_t*)g->cols)[e];
+                if (a >= b) {
+                    inc = 0;
+                    break;
+                }
+            }
+        rg->sorted = inc;
     }
     HIPCHK(ensure(c->in_off, 4ull * (g->n + 1)));
     HIPCHK(ensure(c->in_col, (size_t)g->col_bytes * (g->nnz ? g->nnz : 1)));

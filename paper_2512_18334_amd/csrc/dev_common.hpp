@@ -251,7 +251,8 @@ struct Deg {
 // entries at a time are inserted (a repeat inside the chunk meets its twin),
 // and the rest of the row is looked up against them.  tbl is this wave's
 // ROWCHK_TBL words of LDS.  Returns ROWCHK_ENTRY and/or ROWCHK_REPEAT, the
-// same on every lane.
+// same on every lane, plus ROWCHK_UNSORTED when the row is not strictly
+// increasing.
 // (4 waves of a block take 16 KB: the validation runs beside a resident
 // search kernel, which leaves 32 KB of LDS per CU to the side stream)
 constexpr uint32_t ROWCHK_TBL = 1024u;    // LDS words per wave
@@ -259,6 +260,7 @@ constexpr uint32_t ROWCHK_CHUNK = 512u;   // entries per pass (load <= 1/2)
 constexpr uint32_t ROWCHK_EMPTY = 0xFFFFFFFFu;
 constexpr uint32_t ROWCHK_ENTRY = 1u;     // an entry out of range or equal to v
 constexpr uint32_t ROWCHK_REPEAT = 2u;    // an entry repeated in the row
+constexpr uint32_t ROWCHK_UNSORTED = 4u;  // the row is not strictly increasing
 
 __device__ __forceinline__ uint32_t rowchk_slot(uint32_t w) {
     return (w * 0x9E3779B1u) >> 22;  // 10 bits: ROWCHK_TBL slots
@@ -320,6 +322,7 @@ __device__ __forceinline__ uint32_t wave_row_check(uint32_t v, uint32_t ni, uint
         }
     }
     uint32_t out = 0;
+    if (ballot(unsorted) != 0ull) out |= ROWCHK_UNSORTED;
     if (ballot(bad & ROWCHK_ENTRY) != 0ull) out |= ROWCHK_ENTRY;
     if (ballot(bad & ROWCHK_REPEAT) != 0ull) out |= ROWCHK_REPEAT;
     return out;

@@ -87,6 +87,7 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
     auto cl = [col](uint32_t e) -> uint32_t { return (uint32_t)col[e]; };
     uint64_t acc = 0;
     uint32_t bad = 0;
+    bool uns = false;
     for (uint32_t base = wave * 64u; base < n; base += waves * 64u) {
         const uint32_t v = base + l;
         const uint32_t r0 = v < n ? off[v] : 0u, r1 = v < n ? off[v + 1] : 0u;
@@ -100,10 +101,12 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
                 if (e > r0 && (uint32_t)col[e - 1] >= w) sorted = false;
                 acc += hash(v, w);
             }
-            if (!sorted)
+            if (!sorted) {
+                uns = true;
                 for (uint32_t e = r0; e < r1; ++e)
                     for (uint32_t f = e + 1; f < r1; ++f)
                         if (col[e] == col[f]) bad |= 16u;
+            }
         }
         uint64_t m = ballot(longrow);
         while (m) {
@@ -113,9 +116,11 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
                                               tbl, &acc);
             if (r & ROWCHK_ENTRY) bad |= 4u;
             if (r & ROWCHK_REPEAT) bad |= 16u;
+            if (r & ROWCHK_UNSORTED) uns = true;
         }
     }
     if (bad) atomicOr(&ctr[CTR_INVALID], bad);
+    if (ballot(uns) != 0ull && l == 0) atomicOr(&ctr[CTR_UNSORTED], 1u);
     acc = wave_sum64(acc);
     if (l == 0 && acc) atomicAdd(hsum, (unsigned long long)acc);
 }
@@ -225,12 +230,25 @@ __global__ void k_greedy_rest(uint32_t n, const uint32_t* rdeg, uint32_t* gdeg, 
 // tie-breaks as the search kernel), mark (flags -> in the cover), remove
 // edges.  The bound is best0 - |S_root| - 1.
 
+// is {u, w} an edge: the shorter row is searched, by bisection when every
+// row is strictly increasing (power-law graphs pair hubs with long rows)
 template <typename C>
 __device__ __forceinline__ bool r_adjacent(const uint32_t* off, const C* col, uint32_t u,
-                                           uint32_t w) {
+                                           uint32_t w, int sorted) {
     uint32_t a = u, b = w;
     if (off[w + 1] - off[w] < off[u + 1] - off[u]) { a = w; b = u; }
-    for (uint32_t e = off[a]; e < off[a + 1]; ++e)
+    uint32_t lo = off[a], hi = off[a + 1];
+    if (sorted) {
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo) >> 1);
+            const uint32_t x = (uint32_t)col[mid];
+            if (x == b) return true;
+            if (x < b) lo = mid + 1u;
+            else hi = mid;
+        }
+        return false;
+    }
+    for (uint32_t e = lo; e < hi; ++e)
         if ((uint32_t)col[e] == b) return true;
     return false;
 }
@@ -238,7 +256,7 @@ __device__ __forceinline__ bool r_adjacent(const uint32_t* off, const C* col, ui
 template <typename C>
 __global__ void k_reduce_decide(uint32_t n, const uint32_t* off, const C* col,
                                 const uint32_t* rdeg, uint8_t* addf, uint32_t* ctr,
-                                uint32_t round, int best0) {
+                                uint32_t round, int best0, int sorted) {
     const int s = (int)ctr[CTR_SROOT];
     const int64_t b = (int64_t)best0 - s - 1;
     uint32_t fired = 0;
@@ -266,7 +284,7 @@ __global__ void k_reduce_decide(uint32_t n, const uint32_t* off, const C* col,
                 addf[u] = 1;
                 ++fired;
             }
-        } else if (r_adjacent(off, col, u, w)) {
+        } else if (r_adjacent(off, col, u, w, sorted)) {
             if (!(rdeg[u] == 2u && u < v) && !(rdeg[w] == 2u && w < v)) {
                 addf[u] = 1;
                 addf[w] = 1;
@@ -494,7 +512,7 @@ static inline uint32_t grid_for_waves(uint64_t n) {
 }
 
 hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* hsum,
-                         hipStream_t st, uint32_t* bad_host) {
+                         hipStream_t st, uint32_t* bad_host, int* sorted_host) {
     hipError_t e;
     hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, g.nnz,
                        g.off, ctr);
@@ -514,11 +532,14 @@ hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* 
                            g.off, (const uint32_t*)g.col, ctr, hsum);
     if ((e = hipGetLastError())) return e;
     unsigned long long hs = 0;
+    uint32_t uns = 1;
     if ((e = hipMemcpyAsync(&bad, ctr + CTR_INVALID, 4, hipMemcpyDeviceToHost, st))) return e;
+    if ((e = hipMemcpyAsync(&uns, ctr + CTR_UNSORTED, 4, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipMemcpyAsync(&hs, hsum, 8, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipStreamSynchronize(st))) return e;
     if (hs != 0) bad |= 64u;
     *bad_host = bad;
+    if (sorted_host) *sorted_host = !bad && uns == 0;
     return hipSuccess;
 }
 
@@ -577,7 +598,7 @@ static hipError_t reduce_t(const RootGraph& g, const RootBufs& b, int best0, hip
     for (;;) {
         for (uint32_t j = 0; j < 4; ++j, ++r) {
             hipLaunchKernelGGL(k_reduce_decide<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
-                               b.rdeg, b.addf, b.ctr, r, best0);
+                               b.rdeg, b.addf, b.ctr, r, best0, g.sorted);
             hipLaunchKernelGGL(k_reduce_mark, dim3(grid), dim3(256), 0, st, g.n, b.rdeg, b.addf,
                                b.newly, b.ctr, r);
             hipLaunchKernelGGL(k_reduce_remove<C>, dim3(grid_for_waves(g.n)), dim3(256), 0, st,

@@ -9,6 +9,7 @@ namespace vc {
 // device counters (uint32 slots of RootBufs::ctr)
 enum {
     CTR_INVALID = 0,    // validation failure bits
+    CTR_UNSORTED = 1,   // some row is not strictly increasing
     CTR_SROOT = 2,      // vertices the root reduction put in the cover
     CTR_FIRED = 4,      // rule firings of the last two rounds (2 slots)
     CTR_GLIVE = 6,      // greedy: live vertices seen this round (2 slots)
@@ -28,6 +29,7 @@ struct RootGraph {
     const uint32_t* off;  // device
     const void* col;      // device
     uint32_t col_bytes;
+    int sorted = 0;       // every row strictly increasing (known to the checks)
 };
 
 struct RootBufs {
@@ -50,7 +52,7 @@ struct RootBufs {
 };
 
 hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* hsum,
-                         hipStream_t st, uint32_t* bad_host);
+                         hipStream_t st, uint32_t* bad_host, int* sorted_host = nullptr);
 hipError_t root_init(const RootGraph& g, const RootBufs& b, hipStream_t st);
 hipError_t root_greedy(const RootGraph& g, const RootBufs& b, hipStream_t st, uint32_t* rounds);
 // restart the greedy on the vertices the root rules left (gdeg from rdeg,
