@@ -398,24 +398,28 @@ def config3_chung_lu(seed: int = 3, n: int = 1_000_000, m: int = 5_000_000,
                             name=f"chung_lu_pvc(n={n},m={m},S={s_size})")
 
 
+def config4_instance(i: int, seed: int = 4, n_lo: int = 50, n_hi: int = 800,
+                     d_lo: float = 4.0, d_hi: float = 12.0,
+                     planted_frac: float = 0.25) -> Graph:
+    """Instance i of the uneven batch: G(n, d/(n-1)) or planted |S| = 0.3 n,
+    from its own seed (seed * 1,000,003 + i)."""
+    r = rng(seed * 1_000_003 + i)
+    n = int(r.integers(n_lo, n_hi + 1))
+    d = float(r.uniform(d_lo, d_hi))
+    if r.random() < planted_frac:
+        u, v, S = planted_gnp(n, int(round(0.3 * n)), d, r)
+        return from_edges(n, u, v, f"b{i}_planted", 2, S, {"d": d})
+    iu, ju = np.triu_indices(n, k=1)
+    keep = r.random(iu.size) < d / (n - 1)
+    return from_edges(n, iu[keep], ju[keep], f"b{i}_gnp", 2, None, {"d": d})
+
+
 def config4_batch(seed: int = 4, count: int = 4096, n_lo: int = 50,
                   n_hi: int = 800, d_lo: float = 4.0, d_hi: float = 12.0,
                   planted_frac: float = 0.25) -> list[Graph]:
     """Batch of uneven graphs: G(n, d/(n-1)) or planted |S| = 0.3 n."""
-    out = []
-    for i in range(count):
-        r = rng(seed * 1_000_003 + i)
-        n = int(r.integers(n_lo, n_hi + 1))
-        d = float(r.uniform(d_lo, d_hi))
-        if r.random() < planted_frac:
-            u, v, S = planted_gnp(n, int(round(0.3 * n)), d, r)
-            g = from_edges(n, u, v, f"b{i}_planted", 2, S, {"d": d})
-        else:
-            iu, ju = np.triu_indices(n, k=1)
-            keep = r.random(iu.size) < d / (n - 1)
-            g = from_edges(n, iu[keep], ju[keep], f"b{i}_gnp", 2, None, {"d": d})
-        out.append(g)
-    return out
+    return [config4_instance(i, seed, n_lo, n_hi, d_lo, d_hi, planted_frac)
+            for i in range(count)]
 
 
 def pack_batch(graphs: list[Graph]):
@@ -438,6 +442,24 @@ def pack_batch(graphs: list[Graph]):
     return ns, nnz, ob, cb, offsets, cols
 
 
+def config5_request(i: int, seed: int = 5, n_lo: int = 100, n_hi: int = 100_000,
+                    mean_deg: float = 8.0, gamma: float = 2.3, s_frac: float = 0.06,
+                    mvc_frac: float = 0.7) -> dict:
+    """Request i of the served stream, from its own seed (seed * 1,000,003 +
+    i): a planted Chung-Lu graph of log-uniform size, an MVC request or a PVC
+    request with k = |S| + 1 or |S| - 1 by a seeded coin."""
+    r = rng(seed * 1_000_003 + i)
+    n = int(round(math.exp(r.uniform(math.log(n_lo), math.log(n_hi)))))
+    s = max(1, int(round(s_frac * n)))
+    m = int(round(mean_deg * n / 2))
+    g = chung_lu_planted(n, m, gamma, s, int(r.integers(1 << 62)),
+                         col_bytes=None, name=f"req{i}")
+    if r.random() < mvc_frac:
+        return {"graph": g, "kind": "min", "k": 0}
+    k = s + (1 if r.random() < 0.5 else -1)
+    return {"graph": g, "kind": "param", "k": max(k, 0)}
+
+
 def config5_stream(seed: int = 5, count: int = 2000, n_lo: int = 100,
                    n_hi: int = 100_000, mean_deg: float = 8.0,
                    gamma: float = 2.3, s_frac: float = 0.06,
@@ -448,17 +470,5 @@ def config5_stream(seed: int = 5, count: int = 2000, n_lo: int = 100,
     PVC requests use k = |S| + 1 or |S| - 1 by a seeded coin.  Arrival times
     are drawn by the server from its own rate.
     """
-    out = []
-    for i in range(count):
-        r = rng(seed * 1_000_003 + i)
-        n = int(round(math.exp(r.uniform(math.log(n_lo), math.log(n_hi)))))
-        s = max(1, int(round(s_frac * n)))
-        m = int(round(mean_deg * n / 2))
-        g = chung_lu_planted(n, m, gamma, s, int(r.integers(1 << 62)),
-                             col_bytes=None, name=f"req{i}")
-        if r.random() < mvc_frac:
-            out.append({"graph": g, "kind": "min", "k": 0})
-        else:
-            k = s + (1 if r.random() < 0.5 else -1)
-            out.append({"graph": g, "kind": "param", "k": max(k, 0)})
-    return out
+    return [config5_request(i, seed, n_lo, n_hi, mean_deg, gamma, s_frac, mvc_frac)
+            for i in range(count)]

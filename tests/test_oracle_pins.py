@@ -266,6 +266,49 @@ def test_planted_power_law_pvc(orc):
     assert_cover(g, y["cover"], at_most=r["size"])
 
 
+def _min_degree_matching(g):
+    """A matching built by visiting vertices by increasing degree and pairing
+    each unmatched one with its unmatched neighbour of least degree."""
+    off = g.offsets.astype(np.int64)
+    col = g.cols.astype(np.int64)
+    deg = np.diff(off)
+    mate = np.full(g.n, -1, np.int64)
+    pairs = []
+    for x in np.argsort(deg, kind="stable").tolist():
+        if mate[x] >= 0 or deg[x] == 0:
+            continue
+        nb = col[off[x]:off[x + 1]]
+        free = nb[mate[nb] < 0]
+        if free.size == 0:
+            continue
+        y = int(free[np.argmin(deg[free])])
+        mate[x], mate[y] = y, x
+        pairs.append((x, y))
+    return pairs
+
+
+def test_planted_power_law_full_size_pinned_from_both_sides(orc):
+    """The planted power-law graph at its stated size (n = 10^6, m = 5*10^6,
+    gamma = 2.1, |S| = 60,000): a matching lower-bounds MVC (its edges share
+    no endpoint, so each needs a cover vertex of its own) and any cover bounds
+    it from above.  Here a matching of 59,999 edges meets the oracle's cover
+    of 59,999 vertices, so the exact value is fixed without the oracle's
+    search; PVC flips exactly there."""
+    g = gg.config3_chung_lu()
+    pairs = _min_degree_matching(g)
+    a = np.array([p[0] for p in pairs])
+    b = np.array([p[1] for p in pairs])
+    assert np.unique(np.concatenate([a, b])).size == 2 * len(pairs)
+    adj = {(int(x), int(y)) for x, y in zip(*g.edges())}
+    assert all((min(x, y), max(x, y)) in adj for x, y in pairs)
+    r = orc.mvc(g)
+    assert_cover(g, r["cover"], size=r["size"])
+    assert len(pairs) == r["size"] == 59_999
+    assert r["size"] <= g.planted.size
+    assert not orc.pvc(g, r["size"] - 1)["yes"]
+    assert orc.pvc(g, r["size"])["yes"]
+
+
 def _maximal_matching_size(u, v, alive):
     used = ~alive.copy()
     size = 0
