@@ -8,7 +8,11 @@ m = 7,680, CSR uint32 resident in HBM before the timed region.  One step is
 one vc_min call on it (validation, degrees, greedy bound, root reduction,
 induce, search, cover assembly, the cover copied back).  The line carries
 the HBM-roofline view of the persistent search kernel and the CPU oracle
-timed beside it.
+timed beside it, and (unless --no-legs) the metric's other parts as
+sub-objects: "batch" (the uneven 4,096-graph batch in one launch),
+"serve" (the 2,000-request served stream) and "serve_search_mix" (served
+requests that reach the resident search), each beside the plain
+one-graph-per-call solver and the oracle over the host's cores.
 
 --workload batch: batched graphs/s on the uneven 4,096-graph batch (one
 captured launch per step, a per-instance node limit), with the plain
@@ -81,6 +85,59 @@ def cpu_baseline(g, budget_s: float):
                       f"{el / reps * 1e3:.1f} ms per solve)"}
 
 
+def host_info():
+    """The host's CPU model and the cores this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def _oracle_batch_instance(i):
+    from paper_2512_18334_amd import graphgen as gg
+    import oracle
+    g = gg.config4_instance(i)
+    t0 = time.perf_counter()
+    try:
+        oracle.mvc(g, node_limit=200_000)
+    except oracle.OracleLimit:
+        pass
+    return time.perf_counter() - t0
+
+
+def _served_request(i):
+    from paper_2512_18334_amd import graphgen as gg
+    return gg.config5_request(i)
+
+
+def _oracle_served_request(i):
+    from paper_2512_18334_amd import graphgen as gg
+    import oracle
+    r = gg.config5_request(i)
+    t0 = time.perf_counter()
+    if r["kind"] == "min":
+        oracle.mvc(r["graph"])
+    else:
+        oracle.pvc(r["graph"], r["k"])
+    return time.perf_counter() - t0
+
+
+def pool_map(fn, items, procs):
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(procs) as pool:
+        return pool.map(fn, items, chunksize=4)
+
+
 def roofline(stats_list, search_ms):
     """HBM view of the search kernel: algorithmic bytes per launch (node
     slots written and read back once, the root slot, registry entries,
@@ -114,14 +171,25 @@ def bench_blocks_hubs(args, torch, gg, vc):
         solver.mvc(dg)
     torch.cuda.synchronize()
 
-    stats = []
+    stats, per_call = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        t1 = time.perf_counter()
         r = solver.mvc(dg)
+        per_call.append(time.perf_counter() - t1)
         stats.append(r.stats)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     size = r.size
+    # time to solution from host memory: upload, solve, cover copied back
+    # (outside the timed steps)
+    import numpy as np
+    host_ms = []
+    for _ in range(50):
+        t1 = time.perf_counter()
+        solver.mvc(g)
+        host_ms.append((time.perf_counter() - t1) * 1e3)
+    dev_ms = np.array(per_call) * 1e3
 
     nodes = sum(s["tree_nodes"] for s in stats)
     ms_step = el * 1e3 / args.steps
@@ -147,6 +215,11 @@ def bench_blocks_hubs(args, torch, gg, vc):
                    "deg_bytes": s0["deg_bytes"],
                    "component_branches_per_solve":
                        sum(s["component_branches"] for s in stats) / len(stats),
+                   "tts_resident_ms_p50": float(np.percentile(dev_ms, 50)),
+                   "tts_resident_ms_p90": float(np.percentile(dev_ms, 90)),
+                   "tts_host_input_ms_p50": float(np.percentile(host_ms, 50)),
+                   "tts_host_input_ms_p90": float(np.percentile(host_ms, 90)),
+                   "idle_pct": cycle_breakdown(stats).get("idle", 0.0),
                    "cycle_breakdown_pct": cycle_breakdown(stats)},
         "roofline": roofline(stats, search_ms),
     }
@@ -159,8 +232,214 @@ def bench_blocks_hubs(args, torch, gg, vc):
         out["config"]["calibration_copy_mib"] = args.copy_mib
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+        model, cores = host_info()
+        out["cpu_baseline"]["host_cpu"] = model
+        out["cpu_baseline"]["host_cores"] = cores
     solver.close()
+    if not args.no_legs:
+        # the metric's other parts: batched graphs/s and served p50/p99
+        print("bench: batch leg", file=sys.stderr, flush=True)
+        out["batch"] = leg_batch(args, torch, gg, vc)
+        print("bench: served stream leg", file=sys.stderr, flush=True)
+        items = served_stream_items(vc)
+        out["serve"] = leg_serve(args, torch, gg, vc, items, "served_stream_2000")
+        if not args.no_cpu_baseline:
+            model, cores = host_info()
+            t0 = time.perf_counter()
+            pool_map(_oracle_served_request, list(range(len(items))), cores)
+            dt = time.perf_counter() - t0
+            out["serve"]["cpu_pool_baseline"] = {
+                "value": len(items) / dt, "unit": "solves/s", "cores": cores,
+                "kind": "oracle",
+                "sample": f"all {len(items)} requests, one process per core ({dt:.1f} s)"}
+        del items
+        print("bench: served search-mix leg", file=sys.stderr, flush=True)
+        out["serve_search_mix"] = leg_serve(args, torch, gg, vc, search_mix_items(gg, vc),
+                                            "served_gnp60_and_blocks_mix_300", calib=100)
     return out
+
+
+GOLDEN_BATCH = os.path.join(ROOT, "tests", "golden", "batch4096_oracle.txt")
+
+
+def leg_batch(args, torch, gg, vc):
+    """The uneven 4,096-graph batch in one captured persistent launch, each
+    instance capped at 200,000 tree nodes (the oracle's stored answers under
+    the same cap give the agreement), beside the plain one-graph-per-launch
+    solver on a prefix and the oracle over the host's cores on a sample."""
+    import numpy as np
+    cap = 200_000
+    gs = gg.config4_batch()
+    b = vc.Batch.from_graphs(gs).to_device("cuda:0")
+    torch.cuda.synchronize()
+    with vc.Solver(0, node_limit=cap, watchdog_ms=120_000) as s:
+        t0 = time.perf_counter()
+        r = s.mvc_batch(b, want_cover=False)
+        el = time.perf_counter() - t0
+        st = r.stats
+    ok = r.status == vc.VC_OK
+    gold = {}
+    try:
+        with open(GOLDEN_BATCH) as f:
+            for line in f:
+                if not line.startswith("#"):
+                    x = line.split()
+                    gold[int(x[0])] = (x[4], int(x[5]))
+    except OSError:
+        pass
+    both = sum(1 for i in range(len(gs)) if ok[i] and gold.get(i, ("", 0))[0] == "exact")
+    agree = sum(1 for i in range(len(gs))
+                if ok[i] and gold.get(i, ("", 0))[0] == "exact" and int(r.sizes[i]) == gold[i][1])
+    nplain = 256
+    dgs = [vc.DeviceGraph.from_graph(g, "cuda:0") for g in gs[:nplain]]
+    torch.cuda.synchronize()
+    with vc.Solver(0, node_limit=cap, watchdog_ms=120_000) as plain:
+        t1 = time.perf_counter()
+        for dg in dgs:
+            try:
+                plain.mvc(dg, want_cover=False)
+            except vc.VCError as e:
+                if e.status != vc.VC_ETIMEDOUT:
+                    raise
+        pel = time.perf_counter() - t1
+    out = {"workload": "mvc_batch_4096_uneven", "count": len(gs),
+           "node_limit_per_instance": cap, "graphs_per_s": len(gs) / el,
+           "exact_graphs_per_s": int(ok.sum()) / el, "s_per_launch": el,
+           "instances_exact": int(ok.sum()), "instances_at_limit": int((~ok).sum()),
+           "oracle_exact_under_same_limit": sum(1 for v in gold.values() if v[0] == "exact"),
+           "agree_with_oracle": f"{agree}/{both}",
+           "search_nodes_per_s": st["tree_nodes"] / (st["ms_search"] * 1e-3),
+           "plain_graphs_per_s": nplain / pel, "plain_prefix": nplain}
+    if not args.no_cpu_baseline:
+        model, cores = host_info()
+        sample = list(range(128))
+        t0 = time.perf_counter()
+        pool_map(_oracle_batch_instance, sample, cores)
+        dt = time.perf_counter() - t0
+        out["cpu_pool_baseline"] = {"value": len(sample) / dt, "unit": "graphs/s",
+                                    "cores": cores, "kind": "oracle",
+                                    "sample": f"instances 0-127, same node limit, "
+                                              f"one process per core ({dt:.1f} s)"}
+    return out
+
+
+def _fifo_plain(solver, dev, items, arrive, vc):
+    """The plain solver serving the same arrivals first come first served,
+    measured: each request starts when it has arrived and the previous one
+    is done."""
+    import numpy as np
+    lat, answers = [], []
+    t0 = time.perf_counter()
+    for j, (g, kind, k) in enumerate(items):
+        while time.perf_counter() - t0 < arrive[j]:
+            pass
+        if kind == vc.VC_MIN:
+            answers.append(solver.mvc(dev[j]).size)
+        else:
+            answers.append(bool(solver.pvc(dev[j], k).yes))
+        lat.append((time.perf_counter() - t0 - arrive[j]) * 1e3)
+    return np.array(lat), answers, time.perf_counter() - t0
+
+
+def _serve_stream(solver, dev, items, arrive, vc):
+    """Submit at the arrival times, poll until every request is answered;
+    returns latencies (ms), answers and the span (first arrival to last
+    completion, s)."""
+    import numpy as np
+    served = [None] * len(items)
+    pending = {}
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(items) or pending:
+        now = time.perf_counter() - t0
+        while i < len(items) and arrive[i] <= now:
+            _, kind, k = items[i]
+            pending[solver.submit(dev[i], kind, k)] = i
+            i += 1
+        for tk in list(pending):
+            r = solver.poll(tk, items[pending[tk]][0].n)
+            if r is not None:
+                j = pending.pop(tk)
+                served[j] = (r[0], time.perf_counter() - t0)
+        time.sleep(0.0001)
+    lat = np.array([served[j][1] - arrive[j] for j in range(len(items))]) * 1e3
+    ans = [s[0]["size"] if items[j][1] == vc.VC_MIN else bool(s[0]["yes"])
+           for j, s in enumerate(served)]
+    span = max(s[1] for s in served) - arrive[0]
+    return lat, ans, span
+
+
+def _wait_idle(solver, gg, vc):
+    while True:  # until the resident launch is closed
+        try:
+            solver.mvc(gg.path(3), want_cover=False)
+            return
+        except vc.VCError as e:
+            if e.status != vc.VC_EAGAIN:
+                raise
+            time.sleep(0.002)
+
+
+def leg_serve(args, torch, gg, vc, items, label, calib=200):
+    """A served stream at a fixed Poisson rate: 0.8 x the plain solver's
+    measured solves/s on the first `calib` requests.  p50/p99 latency and
+    solves/s, served (continuous batching) and plain first come first served
+    under the same arrivals, both measured; answers compared."""
+    import numpy as np
+    dev = [vc.DeviceGraph.from_graph(g, "cuda:0") for g, _, _ in items]
+    torch.cuda.synchronize()
+    with vc.Solver(0, node_limit=20_000_000, watchdog_ms=120_000) as s:
+        t0 = time.perf_counter()
+        for j in range(min(calib, len(items))):
+            g, kind, k = items[j]
+            if kind == vc.VC_MIN:
+                s.mvc(dev[j], want_cover=False)
+            else:
+                s.pvc(dev[j], k, want_cover=False)
+        plain_rate = min(calib, len(items)) / (time.perf_counter() - t0)
+        rate = 0.8 * plain_rate
+        arrive = np.cumsum(np.random.default_rng(12345).exponential(1.0 / rate, len(items)))
+        arrive -= arrive[0]
+        t = s.submit(dev[0], items[0][1], items[0][2])  # warm up the server
+        s.wait(t, items[0][0].n)
+        _wait_idle(s, gg, vc)
+        lat, ans, span = _serve_stream(s, dev, items, arrive, vc)
+        _wait_idle(s, gg, vc)
+        plat, pans, pspan = _fifo_plain(s, dev, items, arrive, vc)
+    same = sum(int(a == b) for a, b in zip(ans, pans))
+    return {"workload": label, "requests": len(items), "rate_per_s": rate,
+            "rate_rule": f"0.8 x plain solves/s on {min(calib, len(items))} requests",
+            "solves_per_s": len(items) / span,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "plain_fifo_solves_per_s": len(items) / pspan,
+            "plain_fifo_p50_ms": float(np.percentile(plat, 50)),
+            "plain_fifo_p99_ms": float(np.percentile(plat, 99)),
+            "same_answer_served_and_plain": f"{same}/{len(items)}"}
+
+
+def served_stream_items(vc, count=2000):
+    """The served stream's requests, generated over the host's cores."""
+    model, cores = host_info()
+    reqs = pool_map(_served_request, list(range(count)), min(cores, 16))
+    return [(r["graph"], vc.VC_MIN if r["kind"] == "min" else vc.VC_PARAM, r["k"])
+            for r in reqs]
+
+
+def search_mix_items(gg, vc, count=300):
+    """Requests that reach the resident search: G(60, p) graphs (p from 0.08
+    to 0.12) and small blocks-and-hubs graphs (4 blocks of 48, 2 hubs), all
+    MVC, in a seeded order."""
+    import numpy as np
+    r = np.random.default_rng(77)
+    items = []
+    for i in range(count):
+        if r.random() < 0.8:
+            g = gg.gnp(60, float(r.uniform(0.08, 0.12)), seed=1000 + i)
+        else:
+            g = gg.config2_blocks_hubs(seed=2000 + i, nblocks=4, bsize=48, nhubs=2,
+                                       per_block=10)
+        items.append((g, vc.VC_MIN, 0))
+    return items
 
 
 def bench_batch(args, torch, gg, vc):
@@ -486,6 +765,8 @@ def main():
                     default="blocks_hubs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default workload only: skip the batch and served legs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device to "
                          "device once: a kernel of known traffic that scales "

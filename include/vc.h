@@ -87,6 +87,19 @@ typedef struct {
                                    4096 vertices)                           */
 #define VC_OPT_NO_CROWN 256u    /* single solves: never run the crown
                                    reduction                                */
+#define VC_OPT_STRONG_ORDER 512u /* add agent-scope release fences before
+                                   every publication of a node, cover or
+                                   registry update and acquire fences after
+                                   every consumption, on top of the
+                                   coherent accesses and completion waits
+                                   the search always uses (all entry
+                                   points)                                  */
+#define VC_OPT_CHECK_REGISTRY 1024u /* after a search that ran to its end,
+                                   read the component branch registry back
+                                   and check its end state (Sec. III-C):
+                                   every LiveNodes and LiveComps counter at
+                                   0 and every entry completed exactly once;
+                                   the result is in vc_stats (single solves) */
 
 /*
  * Tuning knobs.  Zero in any field selects the library default.
@@ -174,17 +187,48 @@ typedef struct {
     uint32_t crown_cover;        /* vertices crowns put in the cover (|H|)  */
     uint32_t crown_removed;      /* vertices crowns removed (|I|)           */
     uint32_t crown_rounds;       /* crowns found at the root                */
+    uint64_t stale_reads;        /* worklist reads that saw an older payload
+                                    of the slot and read it again            */
+    uint32_t reg_entries;        /* registry entries allocated by the search */
+    uint32_t reg_checked;        /* 1: the registry end state was checked
+                                    (VC_OPT_CHECK_REGISTRY, search complete) */
+    uint32_t reg_open;           /* entries found not completed exactly once
+                                    or with a counter not back at 0 (0 when
+                                    the protocol held)                       */
+    uint32_t reg_parents;        /* parent entries (branches on components) */
+    uint32_t reg_depth;          /* deepest nesting of branches on components
+                                    (1: none inside a component)             */
+    uint32_t lists_in_hbm;       /* 1: the induced subgraph was too large for
+                                    the workers' lists in LDS, which were
+                                    kept in HBM (Sec. IV-A)                  */
 } vc_stats;
 
 typedef struct vc_ctx vc_ctx;
 
 /*
- * Create a context on HIP device `device`.  `stream` is a hipStream_t to run
- * on (NULL: the library creates its own non-blocking stream); the caller
- * keeps ownership of a stream it passes.  `opts` may be NULL.
+ * Create a context on HIP device `device`.
+ *   stream       a hipStream_t to run on; the caller keeps ownership, and
+ *                orders its writes to device inputs before each call on
+ *                that stream.  NULL: the library creates its own
+ *                non-blocking stream, which before reading device inputs
+ *                waits for the legacy default stream (so inputs written on
+ *                the default stream, PyTorch's default among them, are
+ *                complete).
+ *   arena        NULL with arena_bytes == 0: device buffers come from
+ *                hipMalloc and grow on demand.  Otherwise caller-owned
+ *                device memory of this device (for example a PyTorch uint8
+ *                tensor), arena_bytes long, that must outlive the context:
+ *                every device buffer of the context is carved from it and
+ *                the library allocates no device memory.  The blocking calls
+ *                reuse the arena from its start (nothing is kept between
+ *                them); a call whose buffers do not fit returns VC_ENOMEM.
+ *                Served requests carve from it too, until the next blocking
+ *                call.  VC_EINVAL if only one of the two is given or the
+ *                pointer is not device memory of `device`.
+ *   opts         may be NULL (defaults).
  */
-vc_status vc_ctx_create(int device, void *stream, const vc_opts *opts,
-                        vc_ctx **out);
+vc_status vc_ctx_create(int device, void *stream, void *arena, uint64_t arena_bytes,
+                        const vc_opts *opts, vc_ctx **out);
 
 /* Release every device buffer of the context; ctx may be NULL. */
 vc_status vc_ctx_destroy(vc_ctx *ctx);

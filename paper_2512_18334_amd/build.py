@@ -18,13 +18,17 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvc.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 # (source, object name, extra flags); the search worker is built once per
-# degree-array type so the three instantiations compile in parallel
+# degree-array type, with its lists in LDS and in HBM, so the six
+# instantiations compile in parallel
 SOURCES = [("api.hip", "api", []), ("batch.hip", "batch", []), ("root.hip", "root", []),
            ("crown.hip", "crown", []), ("enum.hip", "enum", []),
            ("search.hip", "search", []), ("serve.hip", "serve", []),
            ("search_deg.hip", "search_d1", ["-DVC_DEG_BYTES=1"]),
            ("search_deg.hip", "search_d2", ["-DVC_DEG_BYTES=2"]),
-           ("search_deg.hip", "search_d4", ["-DVC_DEG_BYTES=4"])]
+           ("search_deg.hip", "search_d4", ["-DVC_DEG_BYTES=4"]),
+           ("search_deg.hip", "search_d1h", ["-DVC_DEG_BYTES=1", "-DVC_HL=1"]),
+           ("search_deg.hip", "search_d2h", ["-DVC_DEG_BYTES=2", "-DVC_HL=1"]),
+           ("search_deg.hip", "search_d4h", ["-DVC_DEG_BYTES=4", "-DVC_HL=1"])]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

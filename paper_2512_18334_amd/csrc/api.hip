@@ -92,6 +92,75 @@ vc_status plan_workers(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* l
     return VC_OK;
 }
 
+vc_status plan_workers_hl(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* lp,
+                          uint32_t* gwords_out, uint32_t* workers_out, uint64_t* hl_bytes) {
+    const uint32_t cus = (uint32_t)(c->cus > 0 ? c->cus : 1);
+    uint32_t workers = c->opts.workers ? c->opts.workers : cus;
+    const uint32_t base_lds = lds_plan_hl(n_pad, deg_bytes, 0, hl_bytes).bytes;
+    uint32_t gwords = c->opts.gcache_words;
+    if (!gwords) {
+        const uint32_t cu_lds = (uint32_t)(c->lds_max < 163840 ? c->lds_max : 163840);
+        const uint32_t per = (workers + cus - 1u) / cus;
+        const uint32_t share = cu_lds / (per ? per : 1u);
+        gwords = share > base_lds + 4096u
+                     ? std::min<uint32_t>(16384u, (share - base_lds - 64u) / 4u) : 0u;
+    }
+    *lp = lds_plan_hl(n_pad, deg_bytes, gwords, hl_bytes);
+    if (lp->bytes > c->lds_max) return VC_ERANGE;
+    int bpc = 0;
+    HIPCHK(search_occupancy(deg_bytes, lp->bytes, &bpc, true));
+    if (bpc < 1) return VC_ERANGE;
+    if (workers > (uint32_t)bpc * cus) workers = (uint32_t)bpc * cus;
+    *gwords_out = gwords;
+    *workers_out = workers;
+    return VC_OK;
+}
+
+}  // namespace vc
+
+namespace vc {
+
+// End state of the component branch registry after a search that ran to
+// its end (Sec. III-C).  Allocations are contiguous blocks from `first`
+// on: a parent entry p with nchild = c >= 2, its children p+1 .. p+c, and
+// one padding entry when c+1 is odd.  Every parent and child must have
+// been completed exactly once (the `done` count) with its LiveComps or
+// LiveNodes counter back at 0.  Returns the entries that are not.
+uint32_t registry_open_entries(const std::vector<RegEntry>& ents, uint32_t first,
+                               uint32_t* parents, uint32_t* max_depth) {
+    uint32_t bad = 0, np = 0, dmax = 0;
+    const uint32_t used = (uint32_t)ents.size();
+    // nesting depth of each parent: one more than the parent of the scope it
+    // branched in (a root scope's branches are at depth 1)
+    std::vector<uint32_t> depth(used, 0);
+    for (uint32_t i = first; i < used;) {
+        const RegEntry& p = ents[i];
+        if (p.nchild < 2 || i + (uint32_t)p.nchild >= used) {
+            ++bad;  // not a parent where one must start
+            break;
+        }
+        ++np;
+        const int a = p.up;  // the scope (a child entry, or a root) it branched in
+        uint32_t d = 1;
+        if (a >= (int)first && a < (int)used) {
+            const int gp = ents[a].up;
+            if (gp >= (int)first && gp < (int)i) d = depth[gp] + 1u;
+            else ++bad;
+        }
+        depth[i] = d;
+        dmax = d > dmax ? d : dmax;
+        if (p.live != 0 || p.done != 1) ++bad;
+        for (int j = 1; j <= p.nchild; ++j) {
+            const RegEntry& ch = ents[i + j];
+            if (ch.live != 0 || ch.done != 1 || ch.up != (int)i || ch.nchild != 0) ++bad;
+        }
+        i += ((uint32_t)p.nchild + 2u) & ~1u;
+    }
+    *parents = np;
+    *max_depth = dmax;
+    return bad;
+}
+
 }  // namespace vc
 
 namespace {
@@ -101,8 +170,8 @@ namespace {
 constexpr uint32_t CROWN_AUTO_MIN = 4096;
 
 vc_status device_validate(vc_ctx* c, const RootGraph& rg, int* sorted = nullptr) {
-    HIPCHK(ensure(c->ctr, CTR_COUNT * 4));
-    HIPCHK(ensure(c->hsum, 8));
+    HIPCHK(ensure(c->pool, c->ctr, CTR_COUNT * 4));
+    HIPCHK(ensure(c->pool, c->hsum, 8));
     HIPCHK(hipMemsetAsync(c->ctr.p, 0, CTR_COUNT * 4, c->stream));
     HIPCHK(hipMemsetAsync(c->hsum.p, 0, 8, c->stream));
     uint32_t bad = 0;
@@ -122,6 +191,8 @@ vc_status stage_graph(vc_ctx* c, const vc_csr* g, RootGraph* rg) {
     if (g->flags & VC_CSR_DEVICE) {
         rg->off = g->offsets;
         rg->col = g->cols;
+        st = order_after_default(c);
+        if (st) return st;
         if (!skip && g->n) {
             st = device_validate(c, *rg, &rg->sorted);
             if (st) return st;
@@ -146,8 +217,8 @@ vc_status stage_graph(vc_ctx* c, const vc_csr* g, RootGraph* rg) {
             }
         rg->sorted = inc;
     }
-    HIPCHK(ensure(c->in_off, 4ull * (g->n + 1)));
-    HIPCHK(ensure(c->in_col, (size_t)g->col_bytes * (g->nnz ? g->nnz : 1)));
+    HIPCHK(ensure(c->pool, c->in_off, 4ull * (g->n + 1)));
+    HIPCHK(ensure(c->pool, c->in_col, (size_t)g->col_bytes * (g->nnz ? g->nnz : 1)));
     HIPCHK(hipMemcpyAsync(c->in_off.p, g->offsets, 4ull * (g->n + 1), hipMemcpyHostToDevice,
                           c->stream));
     if (g->nnz)
@@ -160,21 +231,21 @@ vc_status stage_graph(vc_ctx* c, const vc_csr* g, RootGraph* rg) {
 
 vc_status root_buffers(vc_ctx* c, const RootGraph& g, RootBufs* b) {
     const size_t n = g.n, n1 = g.n + 1;
-    HIPCHK(ensure(c->rdeg, 4 * n1));
-    HIPCHK(ensure(c->gdeg, 4 * n1));
-    HIPCHK(ensure(c->gin, n1));
-    HIPCHK(ensure(c->addf, n1));
-    HIPCHK(ensure(c->newly, n1));
-    HIPCHK(ensure(c->flags, 4 * (n1 + 1)));
-    HIPCHK(ensure(c->newid, 4 * (n1 + 1)));
-    HIPCHK(ensure(c->oldid, 4 * n1));
-    HIPCHK(ensure(c->kdeg, 4 * (n1 + 1)));
-    HIPCHK(ensure(c->koff, 4 * (n1 + 1)));
-    HIPCHK(ensure(c->kcol, 4 * (g.nnz ? g.nnz : 1)));
-    HIPCHK(ensure(c->cover, 4 * n1));
-    HIPCHK(ensure(c->scan_tmp, 4 * (n / 2048 + 4)));
-    HIPCHK(ensure(c->ctr, CTR_COUNT * 4));
-    HIPCHK(ensure(c->hsum, 8));
+    HIPCHK(ensure(c->pool, c->rdeg, 4 * n1));
+    HIPCHK(ensure(c->pool, c->gdeg, 4 * n1));
+    HIPCHK(ensure(c->pool, c->gin, n1));
+    HIPCHK(ensure(c->pool, c->addf, n1));
+    HIPCHK(ensure(c->pool, c->newly, n1));
+    HIPCHK(ensure(c->pool, c->flags, 4 * (n1 + 1)));
+    HIPCHK(ensure(c->pool, c->newid, 4 * (n1 + 1)));
+    HIPCHK(ensure(c->pool, c->oldid, 4 * n1));
+    HIPCHK(ensure(c->pool, c->kdeg, 4 * (n1 + 1)));
+    HIPCHK(ensure(c->pool, c->koff, 4 * (n1 + 1)));
+    HIPCHK(ensure(c->pool, c->kcol, 4 * (g.nnz ? g.nnz : 1)));
+    HIPCHK(ensure(c->pool, c->cover, 4 * n1));
+    HIPCHK(ensure(c->pool, c->scan_tmp, 4 * (n / 2048 + 4)));
+    HIPCHK(ensure(c->pool, c->ctr, CTR_COUNT * 4));
+    HIPCHK(ensure(c->pool, c->hsum, 8));
     b->rdeg = (uint32_t*)c->rdeg.p;
     b->gdeg = (uint32_t*)c->gdeg.p;
     b->gin = (uint8_t*)c->gin.p;
@@ -255,8 +326,21 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     stv.root_rounds = rounds;
     stv.forced_root = ghdr[1];
 
+    // answers decided at the root: the root steps' device time ends here
+    auto root_time = [&]() -> vc_status {
+        float ms = 0;
+        HIPCHK(hipEventRecord(c->ev[1], s));
+        HIPCHK(hipEventSynchronize(c->ev[1]));
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        stv.ms_root = ms;
+        return VC_OK;
+    };
     auto finish_with_greedy = [&](int yes) -> vc_status {
         // the greedy cover is the answer (MVC), or a PVC yes within k
+        if (stv.ms_root == 0.0) {
+            const vc_status rt = root_time();
+            if (rt) return rt;
+        }
         HIPCHK(root_cover(rg, b, 0, 0, nullptr, s));
         uint32_t cnt = 0;
         HIPCHK(hipMemcpyAsync(&cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
@@ -271,6 +355,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         return r;
     };
     auto finish_no = [&]() -> vc_status {
+        if (stv.ms_root == 0.0) {
+            const vc_status rt = root_time();
+            if (rt) return rt;
+        }
         out->yes = 0;
         out->size = 0;
         out->cover_count = 0;
@@ -319,7 +407,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     const bool crown = !no_induce && !(fl & VC_OPT_NO_CROWN) &&
                        np >= ((fl & VC_OPT_CROWN) ? 2u : CROWN_AUTO_MIN);
     for (uint32_t it = 0; crown && np >= 2u && it < 16u; ++it) {
-        HIPCHK(ensure(c->crown, 32ull * rg.n));
+        HIPCHK(ensure(c->pool, c->crown, 32ull * rg.n));
         b.cw = (uint32_t*)c->crown.p;
         uint32_t h = 0;
         HIPCHK(root_crown(rg, b, s, &h));
@@ -371,18 +459,25 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         const uint32_t n_pad = (np + 63u) & ~63u;
         LdsPlan lp;
         uint32_t gwords = 0, workers = 0;
+        uint64_t hl_bytes = 0;
         st = plan_workers(c, n_pad, deg_bytes, &lp, &gwords, &workers);
+        // lists too large for LDS: they go to HBM, one region per worker
+        if (st == VC_ERANGE) st = plan_workers_hl(c, n_pad, deg_bytes, &lp, &gwords, &workers,
+                                                  &hl_bytes);
         if (st) return st;
         const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes + 16u;
         uint32_t depth = std::min<uint32_t>(np, (uint32_t)kbest0) + np / 4u + 16u;
-        const uint64_t budget = c->opts.hbm_budget ? c->opts.hbm_budget : (48ull << 30);
-        const uint64_t per_worker = (uint64_t)depth * slot_bytes;
+        const uint32_t wl_cap = c->opts.worklist_cap ? c->opts.worklist_cap
+                                                     : std::max<uint32_t>(1024u, 4u * workers);
+        // the worklist and control block come off the top; stacks take up
+        // to 1/2 of the rest, the registry 1/4, the graph arena 1/16
+        const uint64_t wl_bytes = (uint64_t)wl_cap * (slot_bytes + 8u) + sizeof(Ctl) + (64u << 10);
+        const uint64_t budget = search_budget(c->opts, c->pool, wl_bytes);
+        const uint64_t per_worker = (uint64_t)depth * slot_bytes + hl_bytes;
         uint64_t wmax = (budget / 2) / (per_worker ? per_worker : 1);
         if (wmax < 1) wmax = 1;
         if (workers > wmax) workers = (uint32_t)wmax;
         if (workers < 1) workers = 1;
-        const uint32_t wl_cap = c->opts.worklist_cap ? c->opts.worklist_cap
-                                                     : std::max<uint32_t>(1024u, 4u * workers);
         const uint32_t bm_words = ((np + 31u) / 32u + 31u) & ~31u;  // whole 128-byte lines
         uint64_t reg_cap = c->opts.registry_cap ? c->opts.registry_cap : (1u << 20);
         const uint64_t reg_bytes_each = sizeof(RegEntry) + 4ull * bm_words;
@@ -391,14 +486,15 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         if (reg_cap < 64) reg_cap = 64;
         stv.workers = workers;
 
-        HIPCHK(ensure(c->stacks, (size_t)workers * depth * slot_bytes));
-        HIPCHK(ensure(c->wl_slots, (size_t)wl_cap * slot_bytes));
-        HIPCHK(ensure(c->wl_seq, 8ull * wl_cap));
-        HIPCHK(ensure(c->ctl, sizeof(Ctl)));
-        HIPCHK(ensure(c->reg, sizeof(RegEntry) * reg_cap));
-        HIPCHK(ensure(c->bitmaps, 4ull * bm_words * reg_cap));
+        HIPCHK(ensure(c->pool, c->stacks, (size_t)workers * depth * slot_bytes));
+        if (hl_bytes) HIPCHK(ensure(c->pool, c->hl, (size_t)workers * hl_bytes));
+        HIPCHK(ensure(c->pool, c->wl_slots, (size_t)wl_cap * slot_bytes));
+        HIPCHK(ensure(c->pool, c->wl_seq, 8ull * wl_cap));
+        HIPCHK(ensure(c->pool, c->ctl, sizeof(Ctl)));
+        HIPCHK(ensure(c->pool, c->reg, sizeof(RegEntry) * reg_cap));
+        HIPCHK(ensure(c->pool, c->bitmaps, 4ull * bm_words * reg_cap));
         uint64_t arena_words = std::min<uint64_t>(budget / 16 / 4, 64ull << 20);
-        HIPCHK(ensure(c->arena, 4ull * arena_words));
+        HIPCHK(ensure(c->pool, c->arena, 4ull * arena_words));
 
         SearchArgs a{};
         a.n = np;
@@ -425,10 +521,14 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         a.lds_G = lp.G;
         a.lds_bytes = lp.bytes;
         a.gcache_words = gwords;
+        a.hl = hl_bytes ? 1u : 0u;
+        a.hl_base = hl_bytes ? (uint8_t*)c->hl.p : nullptr;
+        a.hl_stride = hl_bytes;
+        stv.lists_in_hbm = a.hl;
         a.arena = (uint32_t*)c->arena.p;
         a.arena_words = arena_words;
         a.donate_min = c->opts.donate_min ? c->opts.donate_min : 48u;
-        a.strong_fences = getenv("VC_STRONG_FENCES") ? 1u : 0u;
+        a.strong_fences = (c->opts.flags & VC_OPT_STRONG_ORDER) ? 1u : 0u;
         a.pvc = pvc;
         a.k = pvc ? (int)k - (int)sroot : 0;
         a.flags = c->opts.flags;
@@ -471,29 +571,22 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
             c->last = stv;
             return (vc_status)ctl.err;
         }
-        if (getenv("VC_DEBUG") && ctl.stale)
-            fprintf(stderr, "libvc: %llu stale worklist reads were retried\n",
-                    (unsigned long long)ctl.stale);
-        if (getenv("VC_DEBUG_REGISTRY")) {
-            // after a complete MVC search every counter must be back at 0
-            const uint32_t used = std::min<uint32_t>(ctl.reg_next, (uint32_t)reg_cap);
-            // entries whose parent and child counters are all back at zero
+        stv.stale_reads = ctl.stale;
+        const uint32_t used = std::min<uint32_t>(ctl.reg_next, (uint32_t)reg_cap);
+        stv.reg_entries = used > 2u ? used - 2u : 0u;
+        if ((c->opts.flags & VC_OPT_CHECK_REGISTRY) && !ctl.done) {
+            // the search ran to its end: every branch on components was
+            // completed by its last descendant (Sec. III-C)
             std::vector<RegEntry> ents(used);
-            HIPCHK(hipMemcpy(ents.data(), c->reg.p, sizeof(RegEntry) * used,
-                             hipMemcpyDeviceToHost));
-            uint32_t pos = 0, neg = 0, parents = 0;
-            for (uint32_t i = 2; i < used; ++i) {
-                const RegEntry& r = ents[i];
-                if (r.up <= 0 && r.nchild == 0 && r.size == 0) continue;  // padding
-                if (r.nchild > 0) ++parents;
-                if (r.live > 0) ++pos;
-                if (r.live < 0) ++neg;
-            }
-            fprintf(stderr,
-                    "libvc registry: used=%u parents=%u live>0=%u live<0=%u outstanding=%d "
-                    "idle=%d root.best=%d root.cover=%d kbest0=%d done=%d\n",
-                    used, parents, pos, neg, ctl.outstanding, ctl.idle, root.best,
-                    root.cover_size, kbest0, ctl.done);
+            if (used)
+                HIPCHK(hipMemcpyAsync(ents.data(), c->reg.p, sizeof(RegEntry) * used,
+                                      hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            uint32_t parents = 0, depth = 0;
+            stv.reg_open = registry_open_entries(ents, 2u, &parents, &depth);
+            stv.reg_parents = parents;
+            stv.reg_depth = depth;
+            stv.reg_checked = 1;
         }
         if (root.best < kbest0) {
             // internal invariant: the root's bitmap holds a cover of size Best
@@ -547,11 +640,53 @@ vc_status solve_one(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, uint32_t* s
 
 }  // namespace vc
 
+namespace vc {
+
+// every device buffer of a context (teardown and pool resets)
+std::vector<DevBuf*> ctx_buffers(vc_ctx* c) {
+    std::vector<DevBuf*> v = {
+        &c->in_off, &c->in_col, &c->rdeg,    &c->gdeg,   &c->gin,     &c->addf,    &c->newly,
+        &c->flags,  &c->newid,  &c->oldid,   &c->kdeg,   &c->koff,    &c->kcol,    &c->cover,
+        &c->scan_tmp, &c->ctr,  &c->hsum,    &c->crown,  &c->stacks,  &c->wl_slots, &c->wl_seq,
+        &c->ctl,    &c->reg,    &c->bitmaps, &c->arena,  &c->hl,     &c->b_n,     &c->b_nnz,   &c->b_ob,
+        &c->b_cb,   &c->b_gat,  &c->b_rbase, &c->b_cbase, &c->b_k,    &c->b_state, &c->b_nodes,
+        &c->b_bad,  &c->b_hs,   &c->b_cnt,   &c->b_cov};
+    for (auto& b : c->en) v.push_back(&b);
+    return v;
+}
+
+void pool_reset(vc_ctx* c) {
+    if (!c->pool.base) return;
+    for (DevBuf* b : ctx_buffers(c)) forget(*b);
+    if (c->batch_exec) {
+        hipGraphExecDestroy(c->batch_exec);
+        c->batch_exec = nullptr;
+    }
+    c->batch_key.clear();
+    server_forget_buffers(c);
+    c->pool.used = 0;
+}
+
+// Device inputs are read on the context's stream.  A context that made its
+// own stream first waits for the legacy default stream (an event recorded
+// there completes after all earlier work of the blocking streams, PyTorch's
+// default stream among them), so a graph written there is complete.
+vc_status order_after_default(vc_ctx* c) {
+    if (!c->wait_default) return VC_OK;
+    HIPCHK(hipEventRecord(c->ev[5], nullptr));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev[5], 0));
+    return VC_OK;
+}
+
+}  // namespace vc
+
 extern "C" {
 
-vc_status vc_ctx_create(int device, void* stream, const vc_opts* opts, vc_ctx** out) {
+vc_status vc_ctx_create(int device, void* stream, void* arena, uint64_t arena_bytes,
+                        const vc_opts* opts, vc_ctx** out) {
     if (!out) return VC_EINVAL;
     *out = nullptr;
+    if ((arena == nullptr) != (arena_bytes == 0)) return VC_EINVAL;
     int count = 0;
     hipError_t he = hipGetDeviceCount(&count);
     if (he != hipSuccess || device < 0 || device >= count) {
@@ -566,10 +701,23 @@ vc_status vc_ctx_create(int device, void* stream, const vc_opts* opts, vc_ctx** 
             fprintf(stderr, "libvc: hipSetDevice -> %s\n", hipGetErrorString(he));
         return VC_EDEVICE;
     }
+    if (arena) {
+        // the arena must be device memory of this device
+        hipPointerAttribute_t pa{};
+        if (hipPointerGetAttributes(&pa, arena) != hipSuccess ||
+            pa.type != hipMemoryTypeDevice || pa.device != device)
+            return VC_EINVAL;
+    }
     vc_ctx* c = new (std::nothrow) vc_ctx();
     if (!c) return VC_ENOMEM;
     c->device = device;
     if (opts) c->opts = *opts;
+    if (arena) {
+        const uintptr_t a0 = (uintptr_t)arena, a1 = (a0 + 255u) & ~(uintptr_t)255u;
+        c->pool.base = (uint8_t*)a1;
+        c->pool.cap = arena_bytes > (a1 - a0) ? arena_bytes - (a1 - a0) : 0;
+        c->pool.used = 0;
+    }
     hipDeviceProp_t prop;
     he = hipGetDeviceProperties(&prop, device);
     if (he != hipSuccess) {
@@ -595,9 +743,10 @@ vc_status vc_ctx_create(int device, void* stream, const vc_opts* opts, vc_ctx** 
             return VC_EDEVICE;
         }
         c->own_stream = true;
+        c->wait_default = true;
     }
     for (auto& e : c->ev) {
-        he = hipEventCreate(&e);
+        he = hipEventCreateWithFlags(&e, hipEventDefault);
         if (he != hipSuccess) {
             if (getenv("VC_DEBUG"))
                 fprintf(stderr, "libvc: hipEventCreate -> %s\n", hipGetErrorString(he));
@@ -614,18 +763,11 @@ vc_status vc_ctx_destroy(vc_ctx* c) {
     hipSetDevice(c->device);
     server_shutdown(c);
     if (c->stream) hipStreamSynchronize(c->stream);
-    DevBuf* bufs[] = {&c->in_off, &c->in_col, &c->rdeg, &c->gdeg, &c->gin, &c->addf,
-                      &c->newly, &c->flags, &c->newid, &c->oldid, &c->kdeg, &c->koff,
-                      &c->kcol, &c->cover, &c->scan_tmp, &c->ctr, &c->hsum, &c->stacks,
-                      &c->wl_slots, &c->wl_seq, &c->ctl, &c->reg, &c->bitmaps, &c->arena,
-                      &c->b_n, &c->b_nnz, &c->b_ob, &c->b_cb, &c->b_gat, &c->b_rbase,
-                      &c->b_cbase, &c->b_k, &c->b_state, &c->b_nodes, &c->b_bad, &c->b_hs,
-                      &c->b_cnt, &c->b_cov};
     if (c->batch_exec) hipGraphExecDestroy(c->batch_exec);
-    for (DevBuf* b : bufs)
-        if (b->p) hipFree(b->p);
-    for (auto& e : c->ev)
-        if (e) hipEventDestroy(e);
+    for (DevBuf* b : ctx_buffers(c)) release(*b);
+    if (!c->shared_events)
+        for (auto& e : c->ev)
+            if (e) hipEventDestroy(e);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     delete c;
     return VC_OK;
@@ -638,6 +780,11 @@ vc_status vc_validate(vc_ctx* c, const vc_csr* g) {
     if (!c) return VC_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
     if (g->n == 0) return g->nnz == 0 ? VC_OK : VC_EINVAL;
+    if (!server_busy(c)) pool_reset(c);
+    {
+        const vc_status o = order_after_default(c);
+        if (o) return o;
+    }
     RootGraph rg{g->n, g->nnz, g->offsets, g->cols, g->col_bytes};
     return device_validate(c, rg);
 }
@@ -647,6 +794,7 @@ vc_status vc_min(vc_ctx* c, const vc_csr* g, uint32_t* size, uint32_t* cover,
     if (!c || !size) return VC_EINVAL;
     if (server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    pool_reset(c);
     return solve_one(c, g, 0, 0, size, nullptr, cover, cover_len);
 }
 
@@ -655,6 +803,7 @@ vc_status vc_param(vc_ctx* c, const vc_csr* g, uint32_t k, int* yes, uint32_t* c
     if (!c || !yes) return VC_EINVAL;
     if (server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    pool_reset(c);
     return solve_one(c, g, 1, k, nullptr, yes, cover, cover_len);
 }
 

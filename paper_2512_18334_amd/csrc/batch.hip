@@ -168,8 +168,8 @@ struct BatchOut {
 };
 
 template <typename T>
-hipError_t upload(vc::DevBuf& b, const T* src, size_t count, hipStream_t s) {
-    hipError_t e = ensure(b, sizeof(T) * (count ? count : 1));
+hipError_t upload(vc::Pool& pool, vc::DevBuf& b, const T* src, size_t count, hipStream_t s) {
+    hipError_t e = ensure(pool, b, sizeof(T) * (count ? count : 1));
     if (e) return e;
     if (!count) return hipSuccess;
     return hipMemcpyAsync(b.p, src, sizeof(T) * count, hipMemcpyHostToDevice, s);
@@ -237,8 +237,8 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
             for (uint32_t v = 0; v < gi.n; ++v)
                 dmax = std::max(dmax, gi.offsets[v + 1] - gi.offsets[v]);
         }
-        HIPCHK(upload(c->in_off, b->offsets, off_len, s));
-        HIPCHK(ensure(c->in_col, (size_t)b->col_bytes * (col_len ? col_len : 1)));
+        HIPCHK(upload(c->pool, c->in_off, b->offsets, off_len, s));
+        HIPCHK(ensure(c->pool, c->in_col, (size_t)b->col_bytes * (col_len ? col_len : 1)));
         if (col_len)
             HIPCHK(hipMemcpyAsync(c->in_col.p, b->cols, (size_t)b->col_bytes * col_len,
                                   hipMemcpyHostToDevice, s));
@@ -247,17 +247,19 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     } else {
         d_off = b->offsets;
         d_col = b->cols;
+        vc_status o = order_after_default(c);
+        if (o) return o;
     }
-    HIPCHK(upload(c->b_n, b->n, count, s));
-    HIPCHK(upload(c->b_nnz, b->nnz, count, s));
-    HIPCHK(upload(c->b_ob, b->offs_base, count, s));
-    HIPCHK(upload(c->b_cb, b->cols_base, count, s));
-    HIPCHK(upload(c->b_gat, g_at.data(), count, s));
-    HIPCHK(upload(c->b_cbase, out->cbase.data(), count, s));
+    HIPCHK(upload(c->pool, c->b_n, b->n, count, s));
+    HIPCHK(upload(c->pool, c->b_nnz, b->nnz, count, s));
+    HIPCHK(upload(c->pool, c->b_ob, b->offs_base, count, s));
+    HIPCHK(upload(c->pool, c->b_cb, b->cols_base, count, s));
+    HIPCHK(upload(c->pool, c->b_gat, g_at.data(), count, s));
+    HIPCHK(upload(c->pool, c->b_cbase, out->cbase.data(), count, s));
     if (dev_in) {
-        HIPCHK(upload(c->b_rbase, rbase.data(), count + 1u, s));
-        HIPCHK(ensure(c->b_bad, 4ull * count + 4u));  // flags, then the max degree
-        HIPCHK(ensure(c->b_hs, 8ull * count));
+        HIPCHK(upload(c->pool, c->b_rbase, rbase.data(), count + 1u, s));
+        HIPCHK(ensure(c->pool, c->b_bad, 4ull * count + 4u));  // flags, then the max degree
+        HIPCHK(ensure(c->pool, c->b_hs, 8ull * count));
         HIPCHK(zero_u32(c->b_bad.p, count + 1ull, s));
         HIPCHK(zero_u32(c->b_hs.p, 2ull * count, s));
         uint64_t blocks = (std::max<uint64_t>(sum_n, count) + 255u) / 256u;
@@ -289,11 +291,15 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     if (pst) return pst;
     const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes + 16u;
     const uint32_t depth = n_max + n_max / 4u + 16u;
-    const uint64_t budget = c->opts.hbm_budget ? c->opts.hbm_budget : (48ull << 30);
-    const uint64_t wmax = std::max<uint64_t>(1u, (budget / 2) / ((uint64_t)depth * slot_bytes));
-    workers = (uint32_t)std::min<uint64_t>(workers, wmax);
     const uint32_t wl_cap = c->opts.worklist_cap ? c->opts.worklist_cap
                                                  : std::max<uint32_t>(1024u, 4u * workers);
+    // per-instance arrays, the worklist and the instance graphs come off the
+    // top (pool mode); stacks take up to 1/2 of the rest, the registry 1/4
+    const uint64_t fixed = (uint64_t)wl_cap * (slot_bytes + 8u) + sizeof(Ctl) + 4ull * words +
+                           40ull * count + 4ull * sum_n + (64u << 10);
+    const uint64_t budget = search_budget(c->opts, c->pool, fixed);
+    const uint64_t wmax = std::max<uint64_t>(1u, (budget / 2) / ((uint64_t)depth * slot_bytes));
+    workers = (uint32_t)std::min<uint64_t>(workers, wmax);
     const uint32_t bm_words = ((n_max + 31u) / 32u + 31u) & ~31u;
     const uint64_t reg_bytes_each = sizeof(RegEntry) + 4ull * std::max<uint32_t>(bm_words, 1u);
     uint64_t reg_cap = c->opts.registry_cap ? c->opts.registry_cap : (1u << 20);
@@ -310,23 +316,23 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     stv.slot_bytes = slot_bytes;
     stv.bitmap_bytes = 4u * bm_words;
 
-    HIPCHK(ensure(c->stacks, (size_t)workers * depth * slot_bytes));
-    HIPCHK(ensure(c->wl_slots, (size_t)wl_cap * slot_bytes));
-    HIPCHK(ensure(c->wl_seq, 8ull * wl_cap));
-    HIPCHK(ensure(c->ctl, sizeof(Ctl)));
-    HIPCHK(ensure(c->reg, sizeof(RegEntry) * reg_cap));
-    HIPCHK(ensure(c->bitmaps, 4ull * std::max<uint32_t>(bm_words, 1u) * reg_cap));
-    HIPCHK(ensure(c->arena, 4ull * arena_words));
-    HIPCHK(ensure(c->b_state, 4ull * count));
-    HIPCHK(ensure(c->b_nodes, 8ull * count));
-    HIPCHK(ensure(c->b_cnt, 4ull * count));
-    HIPCHK(ensure(c->b_cov, 4ull * std::max<uint64_t>(sum_n, 1u)));
+    HIPCHK(ensure(c->pool, c->stacks, (size_t)workers * depth * slot_bytes));
+    HIPCHK(ensure(c->pool, c->wl_slots, (size_t)wl_cap * slot_bytes));
+    HIPCHK(ensure(c->pool, c->wl_seq, 8ull * wl_cap));
+    HIPCHK(ensure(c->pool, c->ctl, sizeof(Ctl)));
+    HIPCHK(ensure(c->pool, c->reg, sizeof(RegEntry) * reg_cap));
+    HIPCHK(ensure(c->pool, c->bitmaps, 4ull * std::max<uint32_t>(bm_words, 1u) * reg_cap));
+    HIPCHK(ensure(c->pool, c->arena, 4ull * arena_words));
+    HIPCHK(ensure(c->pool, c->b_state, 4ull * count));
+    HIPCHK(ensure(c->pool, c->b_nodes, 8ull * count));
+    HIPCHK(ensure(c->pool, c->b_cnt, 4ull * count));
+    HIPCHK(ensure(c->pool, c->b_cov, 4ull * std::max<uint64_t>(sum_n, 1u)));
     if (pvc) {
         std::vector<int> kk(count);
         for (uint32_t i = 0; i < count; ++i) kk[i] = (int)std::min<uint32_t>(k[i], INT_MAX - 1);
-        HIPCHK(upload(c->b_k, kk.data(), count, s));
+        HIPCHK(upload(c->pool, c->b_k, kk.data(), count, s));
     } else {
-        HIPCHK(ensure(c->b_k, 4ull * count));
+        HIPCHK(ensure(c->pool, c->b_k, 4ull * count));
     }
 
     SearchArgs a{};
@@ -364,7 +370,7 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     a.small_max = (c->opts.flags & VC_OPT_NO_SMALL) ? 0u
                   : std::min<uint32_t>(c->opts.small_max ? c->opts.small_max : 128u, 128u);
     a.donate_min = c->opts.donate_min ? c->opts.donate_min : 48u;
-    a.strong_fences = 0;
+    a.strong_fences = (c->opts.flags & VC_OPT_STRONG_ORDER) ? 1u : 0u;
     a.node_limit = 0;
     a.watchdog_ticks =
         (uint64_t)c->wall_khz * (c->opts.watchdog_ms ? c->opts.watchdog_ms : 120000u);
@@ -465,6 +471,12 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     for (int i = 0; i < 6; ++i) stv.cycles[i] = ctl.cyc[i];
     stv.bytes_nodes = ctl.bytes_nodes;
     stv.bytes_registry = ctl.bytes_registry;
+    stv.stale_reads = ctl.stale;
+    {
+        const uint32_t first = (count + 1u) & ~1u;
+        const uint32_t used = std::min<uint32_t>(ctl.reg_next, (uint32_t)reg_cap);
+        stv.reg_entries = used > first ? used - first : 0u;
+    }
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, c->ev[3], c->ev[4]));
     stv.ms_search = ms;
@@ -498,6 +510,7 @@ vc_status vc_min_batch(vc_ctx* c, const vc_batch* b, uint32_t* sizes, int32_t* i
     if ((covers == nullptr) != (cover_offs == nullptr)) return VC_EINVAL;
     if (server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    pool_reset(c);
     BatchOut o;
     vc_status st = run_batch(c, b, 0, nullptr, &o);
     if (st) return st;
@@ -528,6 +541,7 @@ vc_status vc_param_batch(vc_ctx* c, const vc_batch* b, const uint32_t* k, int* y
     if ((covers == nullptr) != (cover_offs == nullptr)) return VC_EINVAL;
     if (server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    pool_reset(c);
     BatchOut o;
     vc_status st = run_batch(c, b, 1, k, &o);
     if (st) return st;

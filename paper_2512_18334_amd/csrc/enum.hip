@@ -362,14 +362,14 @@ vc_status enum_t(vc_ctx* c, const RootGraph& g, uint32_t k, uint64_t max_covers,
     DevBuf* B = c->en;
     // ctr: 0 changed, 1 max component size, 2 sum of lb, 3 error bits,
     // 4-5 covers of all components (64-bit)
-    HIPCHK(ensure(B[0], 64));
+    HIPCHK(ensure(c->pool, B[0], 64));
     uint32_t* ctr = (uint32_t*)B[0].p;
-    HIPCHK(ensure(B[1], 4ull * n));        // label
-    HIPCHK(ensure(B[2], 4ull * (n + 1)));  // root flags, then component sizes
-    HIPCHK(ensure(B[3], 4ull * (n + 1)));  // rank of each root
-    HIPCHK(ensure(B[4], 4ull * n));        // local ids
-    HIPCHK(ensure(B[5], 4ull * n));        // vertices by component
-    HIPCHK(ensure(B[6], 4ull * (n / 2048 + 4)));  // scan scratch
+    HIPCHK(ensure(c->pool, B[1], 4ull * n));        // label
+    HIPCHK(ensure(c->pool, B[2], 4ull * (n + 1)));  // root flags, then component sizes
+    HIPCHK(ensure(c->pool, B[3], 4ull * (n + 1)));  // rank of each root
+    HIPCHK(ensure(c->pool, B[4], 4ull * n));        // local ids
+    HIPCHK(ensure(c->pool, B[5], 4ull * n));        // vertices by component
+    HIPCHK(ensure(c->pool, B[6], 4ull * (n / 2048 + 4)));  // scan scratch
     uint32_t *label = (uint32_t*)B[1].p, *flag = (uint32_t*)B[2].p, *rank = (uint32_t*)B[3].p;
     uint32_t *loc = (uint32_t*)B[4].p, *verts = (uint32_t*)B[5].p, *tmp = (uint32_t*)B[6].p;
     HIPCHK(hipMemsetAsync(ctr, 0, 64, s));
@@ -400,15 +400,15 @@ vc_status enum_t(vc_ctx* c, const RootGraph& g, uint32_t k, uint64_t max_covers,
     HIPCHK(hipMemcpyAsync(&maxsize, ctr + 1, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (maxsize > EN_MAXC) return VC_ERANGE;
-    HIPCHK(ensure(B[7], 4ull * (ncomp + 1)));  // component offsets
+    HIPCHK(ensure(c->pool, B[7], 4ull * (ncomp + 1)));  // component offsets
     uint32_t* coff = (uint32_t*)B[7].p;
     HIPCHK(scan_u32(csize, ncomp, coff, tmp, s));
     hipLaunchKernelGGL(k_en_place, dim3(grid), dim3(256), 0, s, n, label, rank, loc, coff, verts);
     // lower bounds, then counts by size
-    HIPCHK(ensure(B[8], 4ull * ncomp + 4ull * (ncomp + 1)));  // lb, totals
+    HIPCHK(ensure(c->pool, B[8], 4ull * ncomp + 4ull * (ncomp + 1)));  // lb, totals
     uint32_t* lb = (uint32_t*)B[8].p;
     uint32_t* tot = lb + ncomp;
-    HIPCHK(ensure(B[9], 8ull * 64u * ncomp));
+    HIPCHK(ensure(c->pool, B[9], 8ull * 64u * ncomp));
     uint64_t* cnt = (uint64_t*)B[9].p;
     const uint32_t cgrid = std::min<uint32_t>(ncomp, 65535u);
     hipLaunchKernelGGL(k_en_lb<C>, dim3(cgrid), dim3(64), 0, s, ncomp, g.off, col, loc, verts,
@@ -432,7 +432,7 @@ vc_status enum_t(vc_ctx* c, const RootGraph& g, uint32_t k, uint64_t max_covers,
                        reinterpret_cast<unsigned long long*>(ctr + 4));
     HIPCHK(hipGetLastError());
     // list offsets (the component lists stay below 2^26 entries in all)
-    HIPCHK(ensure(B[10], 4ull * (ncomp + 1)));
+    HIPCHK(ensure(c->pool, B[10], 4ull * (ncomp + 1)));
     uint32_t* loff = (uint32_t*)B[10].p;
     HIPCHK(scan_u32(tot, ncomp, loff, tmp, s));
     uint32_t hdr[4] = {0, 0, 0, 0};
@@ -443,7 +443,7 @@ vc_status enum_t(vc_ctx* c, const RootGraph& g, uint32_t k, uint64_t max_covers,
     if ((hdr[0] & 2u) || nlist > EN_LIST_MAX) return VC_ERANGE;
     const uint64_t wsz = ((uint64_t)ncomp + 1u) * ((uint64_t)k + 1u);
     if (wsz > EN_WAYS_MAX) return VC_ERANGE;
-    HIPCHK(ensure(B[11], 8ull * (nlist ? nlist : 1) + 8ull * wsz));
+    HIPCHK(ensure(c->pool, B[11], 8ull * (nlist ? nlist : 1) + 8ull * wsz));
     uint64_t* list = (uint64_t*)B[11].p;
     uint64_t* ways = list + (nlist ? nlist : 1);
     if (nlist) {
@@ -461,7 +461,7 @@ vc_status enum_t(vc_ctx* c, const RootGraph& g, uint32_t k, uint64_t max_covers,
     *count = total;
     const uint64_t nout = std::min<uint64_t>(total, max_covers);
     if (nout && k) {
-        HIPCHK(ensure(B[12], 4ull * nout * k + 4ull * nout));
+        HIPCHK(ensure(c->pool, B[12], 4ull * nout * k + 4ull * nout));
         uint32_t* dout = (uint32_t*)B[12].p;
         uint32_t* dsz = dout + nout * k;
         hipLaunchKernelGGL(k_en_unrank, dim3(en_grid(nout)), dim3(256), 0, s, nout, ncomp, k, ways,
@@ -486,6 +486,7 @@ extern "C" vc_status vc_param_enum(vc_ctx* c, const vc_csr* g, uint32_t k, uint6
     if (max_covers && ((k && !covers) || !sizes)) return VC_EINVAL;
     if (vc::server_busy(c)) return VC_EAGAIN;
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    vc::pool_reset(c);
     vc::RootGraph rg;
     vc_status st = vc::stage_input(c, g, &rg);
     if (st) return st;

@@ -54,7 +54,8 @@ struct RegEntry {
     int g_nnz;      // own view: CSR entries
     int att;        // parent, PVC: Sum plus the children's attained covers
     int unatt;      // parent, PVC: children without an attained cover yet
-    int pad[3];
+    int done;       // times the entry was completed (VC_OPT_CHECK_REGISTRY)
+    int pad[2];
 };
 static_assert(sizeof(RegEntry) == 64, "registry entry is 64 bytes");
 
@@ -149,6 +150,13 @@ struct SearchArgs {
     uint32_t serve;
     const int* inst_cancel;
     uint32_t small_max;  // live vertices up to which a node is solved in registers (0: never)
+    // Lists in HBM (nodes whose lists do not fit LDS): the live list and the
+    // scratch lists L, Q, R of worker w are at hl_base + w * hl_stride (the
+    // lds_L, lds_Q, lds_R offsets are then offsets in that region); the
+    // degree array, bitmaps, row markers and graph cache stay in LDS.
+    uint32_t hl;
+    uint8_t* hl_base;
+    uint64_t hl_stride;
 };
 
 // LDS layout of one worker: degree array, live list L, scratch lists Q and
@@ -178,12 +186,37 @@ inline LdsPlan lds_plan(uint32_t n_pad, uint32_t sd, uint32_t gcache_words) {
     return p;
 }
 
+// The same layout with the lists L, Q and R moved to a per-worker region of
+// HBM (hl_bytes long, offsets L, Q, R in it): LDS then holds the degree
+// array, the bitmaps, the row markers with the small-node solver's masks,
+// and the graph cache, about sizeof(D) + 1/4 bytes per vertex instead of
+// about sizeof(D) + 16.
+inline LdsPlan lds_plan_hl(uint32_t n_pad, uint32_t sd, uint32_t gcache_words,
+                           uint64_t* hl_bytes) {
+    LdsPlan p;
+    uint32_t at = n_pad * sd;
+    at = (at + 15u) & ~15u;
+    const uint32_t bw = (n_pad + 31u) / 32u;
+    p.VB = at; at += 4u * bw;
+    p.PB = at; at += 4u * bw;
+    at = (at + 15u) & ~15u;
+    p.MK = at; at += 4u * 64u + 8u * 128u * 2u + 8u * 128u * 4u + 4u * 128u;
+    p.G = at; at += 4u * gcache_words;
+    p.bytes = (at + 15u) & ~15u;
+    p.L = 0;
+    p.Q = 4u * n_pad;
+    p.R = 8u * n_pad;
+    *hl_bytes = ((uint64_t)4u * (4u * n_pad + 64u) + 255u) & ~255ull;
+    return p;
+}
+
 // ------------------------------------------------------ kernel launchers
 // (defined in the .hip files; all launch on `st`)
 
 hipError_t launch_search(const SearchArgs& a, uint32_t deg_bytes, uint32_t workers,
                          hipStream_t st);
-hipError_t search_occupancy(uint32_t deg_bytes, uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t search_occupancy(uint32_t deg_bytes, uint32_t lds_bytes, int* blocks_per_cu,
+                            bool hl = false);
 hipError_t launch_search_init(const SearchArgs& a, int best0, uint32_t deg_bytes,
                               const uint32_t* kdeg, hipStream_t st);
 

@@ -66,16 +66,27 @@ __global__ void k_check_offsets(uint32_t n, uint64_t nnz, const uint32_t* off, u
     }
 }
 
-// rows: ids < n, no self-loop, no repeated entry; symmetric (the signed sum
-// of a hash of each unordered pair over all entries vanishes exactly when
-// every entry has its mirror, up to hash collisions)
+// Rows: ids < n, no self-loop, no repeated entry, symmetric.  The entries
+// of 64 consecutive rows are contiguous in the CSR, so a wave walks them flat,
+// 64 entries per step with one coalesced load: each entry finds its row by
+// the marks its row's start leaves in the wave's 64 words of LDS (an
+// inclusive max-scan), and compares itself with the entry before it (the
+// lane to its left, or the last entry of the previous step).  Every entry
+// (v, w) also looks v up in row w by bisection: when every row turns out to
+// be strictly increasing (CTR_UNSORTED stays 0) that is an exact symmetry
+// test, and a miss sets CTR_MIRROR.  Rows that are not strictly increasing
+// are then checked for repeats one by one (a lane per short row, the whole
+// wave per long row), and symmetry falls back to the signed sum of a hash of
+// each unordered pair, which vanishes when every entry has its mirror (an
+// asymmetric graph passes only on a hash collision).
 template <typename C>
 __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* off, const C* col,
                                                     uint32_t* ctr, unsigned long long* hsum) {
-    // 64 consecutive rows per wave, one per lane; a row longer than 32
-    // entries is checked by the whole wave (wave_row_check)
+    // (16 KB: the row marks use the first 64 words of the wave's repeat
+    // table, which is only needed after the flat walk of a block of rows)
     __shared__ uint32_t tbl_all[4 * ROWCHK_TBL];
     uint32_t* tbl = tbl_all + (threadIdx.x >> 6) * ROWCHK_TBL;
+    uint32_t* MK = tbl;
     const uint32_t l = threadIdx.x & 63u;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
@@ -85,42 +96,89 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
         return v < w ? h : (0ull - h);
     };
     auto cl = [col](uint32_t e) -> uint32_t { return (uint32_t)col[e]; };
+    // is v in row w (bisection: meaningful when row w is increasing)
+    auto mirrored = [&](uint32_t w, uint32_t v) -> bool {
+        uint32_t lo = off[w], hi = off[w + 1];
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo) >> 1);
+            const uint32_t x = (uint32_t)col[mid];
+            if (x == v) return true;
+            if (x < v) lo = mid + 1u;
+            else hi = mid;
+        }
+        return false;
+    };
     uint64_t acc = 0;
     uint32_t bad = 0;
-    bool uns = false;
+    bool uns = false, miss = false;
     for (uint32_t base = wave * 64u; base < n; base += waves * 64u) {
         const uint32_t v = base + l;
+        const uint32_t last = (n - base < 64u ? n - base : 64u) - 1u;  // last row's lane
         const uint32_t r0 = v < n ? off[v] : 0u, r1 = v < n ? off[v + 1] : 0u;
-        const bool longrow = r1 - r0 > 32u;
-        if (v < n && !longrow) {
-            bool sorted = true;
-            for (uint32_t e = r0; e < r1; ++e) {
-                const uint32_t w = (uint32_t)col[e];
-                if (w >= n) { bad |= 4u; continue; }
-                if (w == v) bad |= 8u;
-                if (e > r0 && (uint32_t)col[e - 1] >= w) sorted = false;
-                acc += hash(v, w);
+        const uint32_t start = __builtin_amdgcn_readfirstlane(r0);
+        const uint32_t end = __builtin_amdgcn_readlane(r1, last);
+        bool row_uns = false;  // this lane's row is not strictly increasing
+        uint32_t carry = 0, wprev = 0;
+        for (uint32_t t0 = start; t0 < end; t0 += 64u) {
+            wave_sync();  // the previous step's reads of MK are done
+            MK[l] = 0u;
+            wave_sync();
+            if (v < n && r1 > r0 && r0 >= t0 && r0 - t0 < 64u) MK[r0 - t0] = l + 1u;
+            wave_sync();  // every row start is marked
+            uint32_t own = MK[l];
+            VC_DPP_SCAN(own, op_max, 0u);
+            own = own > carry ? own : carry;
+            carry = __builtin_amdgcn_readlane(own, 63);
+            const uint32_t jr = own - 1u;  // lane of this entry's row
+            const uint32_t e = t0 + l;
+            const bool ok = e < end;
+            const uint32_t w = ok ? (uint32_t)col[e] : 0u;
+            const uint32_t rv = base + jr;
+            const uint32_t rs = shfl(r0, jr);
+            // the entry before, in CSR order
+            uint32_t p = shfl(w, l ? l - 1u : 0u);
+            if (l == 0) p = wprev;
+            wprev = __builtin_amdgcn_readlane(w, 63);
+            bool unsorted_here = false;
+            if (ok) {
+                if (w >= n) {
+                    bad |= 4u;
+                } else {
+                    if (w == rv) bad |= 8u;
+                    acc += hash(rv, w);
+                    if (!mirrored(w, rv)) miss = true;
+                }
+                if (e > rs && p >= w) unsorted_here = true;
             }
-            if (!sorted) {
-                uns = true;
-                for (uint32_t e = r0; e < r1; ++e)
-                    for (uint32_t f = e + 1; f < r1; ++f)
-                        if (col[e] == col[f]) bad |= 16u;
+            // tell the row's lane
+            uint64_t um = ballot(unsorted_here);
+            while (um) {
+                const uint32_t k = (uint32_t)__builtin_ctzll(um);
+                um &= um - 1ull;
+                if (l == shfl(jr, k)) row_uns = true;
             }
         }
+        wave_sync();  // the marks are read before the repeat table is reused
+        // repeats, in the rows that are not increasing
+        if (row_uns) uns = true;
+        const bool longrow = row_uns && r1 - r0 > 32u;
+        if (row_uns && !longrow)
+            for (uint32_t e = r0; e < r1; ++e)
+                for (uint32_t f = e + 1; f < r1; ++f)
+                    if (col[e] == col[f]) bad |= 16u;
         uint64_t m = ballot(longrow);
         while (m) {
-            const uint32_t j = (uint32_t)__builtin_ctzll(m);
+            const uint32_t j2 = (uint32_t)__builtin_ctzll(m);
             m &= m - 1ull;
-            const uint32_t r = wave_row_check(base + j, n, shfl(r0, j), shfl(r1, j), cl, hash,
-                                              tbl, &acc);
-            if (r & ROWCHK_ENTRY) bad |= 4u;
+            uint64_t unused = 0;
+            const uint32_t r = wave_row_check(base + j2, n, shfl(r0, j2), shfl(r1, j2), cl, hash,
+                                              tbl, &unused);
             if (r & ROWCHK_REPEAT) bad |= 16u;
-            if (r & ROWCHK_UNSORTED) uns = true;
         }
     }
     if (bad) atomicOr(&ctr[CTR_INVALID], bad);
     if (ballot(uns) != 0ull && l == 0) atomicOr(&ctr[CTR_UNSORTED], 1u);
+    if (ballot(miss) != 0ull && l == 0) atomicOr(&ctr[CTR_MIRROR], 1u);
     acc = wave_sum64(acc);
     if (l == 0 && acc) atomicAdd(hsum, (unsigned long long)acc);
 }
@@ -257,6 +315,9 @@ template <typename C>
 __global__ void k_reduce_decide(uint32_t n, const uint32_t* off, const C* col,
                                 const uint32_t* rdeg, uint8_t* addf, uint32_t* ctr,
                                 uint32_t round, int best0, int sorted) {
+    // the previous round fired nothing: the fixpoint is reached (this
+    // round's count stays 0, so the rest of the group does nothing either)
+    if (round > 0 && ctr[CTR_FIRED + ((round + 1u) & 1u)] == 0) return;
     const int s = (int)ctr[CTR_SROOT];
     const int64_t b = (int64_t)best0 - s - 1;
     uint32_t fired = 0;
@@ -312,18 +373,43 @@ __global__ void k_reduce_mark(uint32_t n, uint32_t* rdeg, uint8_t* addf, uint8_t
     block_atomic_add(&ctr[CTR_SROOT], added);
 }
 
+// Remove the edges of the vertices marked this round: a lane per marked
+// vertex walks a short row, the whole wave a row longer than 16 entries.
 template <typename C>
-__global__ void k_reduce_remove(uint32_t n, const uint32_t* off, const C* col, uint32_t* rdeg,
-                                uint8_t* newly) {
+__global__ void __launch_bounds__(256) k_reduce_remove(uint32_t n, const uint32_t* off,
+                                                       const C* col, uint32_t* rdeg,
+                                                       uint8_t* newly, const uint32_t* ctr,
+                                                       uint32_t round) {
+    if (ctr[CTR_FIRED + (round & 1u)] == 0) return;  // nothing was marked
     const uint32_t l = threadIdx.x & 63u;
-    WAVE_LOOP(v, n) {
-        if (!newly[v]) continue;
-        const uint32_t r1 = off[v + 1];
-        for (uint32_t e = off[v] + l; e < r1; e += 64) {
-            const uint32_t u = (uint32_t)col[e];
-            if (rlive(rdeg[u])) atomicSub(&rdeg[u], 1u);
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t base = wave * 64u; base < n; base += waves * 64u) {
+        const uint32_t v = base + l;
+        const bool nw = v < n && newly[v];
+        uint32_t r0 = 0, r1 = 0;
+        if (nw) {
+            newly[v] = 0;
+            r0 = off[v];
+            r1 = off[v + 1];
         }
-        if (l == 0) newly[v] = 0;
+        const bool longrow = nw && r1 - r0 > 16u;
+        if (nw && !longrow) {
+            for (uint32_t e = r0; e < r1; ++e) {
+                const uint32_t u = (uint32_t)col[e];
+                if (rlive(rdeg[u])) atomicSub(&rdeg[u], 1u);
+            }
+        }
+        uint64_t m = ballot(longrow);
+        while (m) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1ull;
+            const uint32_t a = shfl(r0, j), b = shfl(r1, j);
+            for (uint32_t e = a + l; e < b; e += 64u) {
+                const uint32_t u = (uint32_t)col[e];
+                if (rlive(rdeg[u])) atomicSub(&rdeg[u], 1u);
+            }
+        }
     }
 }
 
@@ -532,12 +618,15 @@ hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* 
                            g.off, (const uint32_t*)g.col, ctr, hsum);
     if ((e = hipGetLastError())) return e;
     unsigned long long hs = 0;
-    uint32_t uns = 1;
+    uint32_t uns = 1, miss = 1;
     if ((e = hipMemcpyAsync(&bad, ctr + CTR_INVALID, 4, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipMemcpyAsync(&uns, ctr + CTR_UNSORTED, 4, hipMemcpyDeviceToHost, st))) return e;
+    if ((e = hipMemcpyAsync(&miss, ctr + CTR_MIRROR, 4, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipMemcpyAsync(&hs, hsum, 8, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipStreamSynchronize(st))) return e;
-    if (hs != 0) bad |= 64u;
+    // increasing rows: the mirror of every entry was looked up (exact);
+    // otherwise the pair-hash sum must vanish
+    if (uns == 0 ? miss != 0 : hs != 0) bad |= 64u;
     *bad_host = bad;
     if (sorted_host) *sorted_host = !bad && uns == 0;
     return hipSuccess;
@@ -601,8 +690,8 @@ static hipError_t reduce_t(const RootGraph& g, const RootBufs& b, int best0, hip
                                b.rdeg, b.addf, b.ctr, r, best0, g.sorted);
             hipLaunchKernelGGL(k_reduce_mark, dim3(grid), dim3(256), 0, st, g.n, b.rdeg, b.addf,
                                b.newly, b.ctr, r);
-            hipLaunchKernelGGL(k_reduce_remove<C>, dim3(grid_for_waves(g.n)), dim3(256), 0, st,
-                               g.n, g.off, col, b.rdeg, b.newly);
+            hipLaunchKernelGGL(k_reduce_remove<C>, dim3(grid), dim3(256), 0, st, g.n, g.off, col,
+                               b.rdeg, b.newly, b.ctr, r);
         }
         if ((e = hipGetLastError())) return e;
         uint32_t fired = 0;

@@ -9,22 +9,39 @@ namespace vc {
 
 #define VC_DECL(sfx)                                                                  \
     hipError_t launch_search_##sfx(const SearchArgs& a, uint32_t workers, hipStream_t st); \
-    hipError_t search_occupancy_##sfx(uint32_t lds_bytes, int* bpc);                  \
-    hipError_t launch_search_init_##sfx(const SearchArgs& a, int best0, const uint32_t* kdeg, \
-                                        uint32_t blocks, hipStream_t st);
+    hipError_t search_occupancy_##sfx(uint32_t lds_bytes, int* bpc);
 VC_DECL(d1)
 VC_DECL(d2)
 VC_DECL(d4)
+VC_DECL(d1h)
+VC_DECL(d2h)
+VC_DECL(d4h)
 #undef VC_DECL
+hipError_t launch_search_init_d1(const SearchArgs& a, int best0, const uint32_t* kdeg,
+                                 uint32_t blocks, hipStream_t st);
+hipError_t launch_search_init_d2(const SearchArgs& a, int best0, const uint32_t* kdeg,
+                                 uint32_t blocks, hipStream_t st);
+hipError_t launch_search_init_d4(const SearchArgs& a, int best0, const uint32_t* kdeg,
+                                 uint32_t blocks, hipStream_t st);
 
 hipError_t launch_search(const SearchArgs& a, uint32_t deg_bytes, uint32_t workers,
                          hipStream_t st) {
+    if (a.hl) {
+        if (deg_bytes == 1) return launch_search_d1h(a, workers, st);
+        if (deg_bytes == 2) return launch_search_d2h(a, workers, st);
+        return launch_search_d4h(a, workers, st);
+    }
     if (deg_bytes == 1) return launch_search_d1(a, workers, st);
     if (deg_bytes == 2) return launch_search_d2(a, workers, st);
     return launch_search_d4(a, workers, st);
 }
 
-hipError_t search_occupancy(uint32_t deg_bytes, uint32_t lds_bytes, int* bpc) {
+hipError_t search_occupancy(uint32_t deg_bytes, uint32_t lds_bytes, int* bpc, bool hl) {
+    if (hl) {
+        if (deg_bytes == 1) return search_occupancy_d1h(lds_bytes, bpc);
+        if (deg_bytes == 2) return search_occupancy_d2h(lds_bytes, bpc);
+        return search_occupancy_d4h(lds_bytes, bpc);
+    }
     if (deg_bytes == 1) return search_occupancy_d1(lds_bytes, bpc);
     if (deg_bytes == 2) return search_occupancy_d2(lds_bytes, bpc);
     return search_occupancy_d4(lds_bytes, bpc);

@@ -47,8 +47,13 @@ __device__ __forceinline__ uint64_t uni(uint64_t x) {
 // that starts there marks its lane at its start position in MK (64 words
 // of LDS), and an inclusive max-scan over the marks gives each entry its
 // row; entries before the first start continue the previous chunk's last
-// row.  f(ok, v, w) is called by all lanes in lock-step; ok is false on
-// padding lanes.
+// row.  The positions of FOR_ROWS_AHEAD chunks are worked out first and
+// their column loads issued together, so a graph read from HBM costs one
+// memory latency per group of chunks rather than per chunk.  f(ok, v, w) is
+// then called by all lanes in lock-step, chunk by chunk in order; ok is
+// false on padding lanes.
+constexpr uint32_t FOR_ROWS_AHEAD = 4;
+
 template <typename Off, typename Col, typename F>
 __device__ __forceinline__ void for_rows(Off&& off, Col&& col, const uint32_t* list,
                                          uint32_t cnt, uint32_t* MK, F&& f) {
@@ -66,27 +71,45 @@ __device__ __forceinline__ void for_rows(Off&& off, Col&& col, const uint32_t* l
         const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
         const uint32_t delta = r0 - excl;  // CSR position of flat entry t is t + delta
         uint32_t carry = 0;                // (lane + 1) of the row running into the chunk
-        for (uint32_t t0 = 0; t0 < total; t0 += 64) {
-            wave_sync();  // the previous chunk's reads of MK are done
-            MK[l] = 0u;
-            if (len && excl >= t0 && excl - t0 < 64u) MK[excl - t0] = l + 1u;
-            wave_sync();  // other lanes' marks are visible
-            uint32_t own = MK[l];
-            VC_DPP_SCAN(own, op_max, 0u);
-            own = own > carry ? own : carry;
-            carry = __builtin_amdgcn_readlane(own, 63);
-            const uint32_t j = own - 1u;
-            const uint32_t t = t0 + l;
-            const bool ok = t < total;
-            const uint32_t vj = shfl(v, j);
-            const uint32_t e = t + shfl(delta, j);
-            const uint32_t w = ok ? col(e) : 0u;
-            f(ok, vj, w);
+        for (uint32_t g0 = 0; g0 < total; g0 += 64u * FOR_ROWS_AHEAD) {
+            uint32_t vv[FOR_ROWS_AHEAD], ee[FOR_ROWS_AHEAD], ww[FOR_ROWS_AHEAD];
+            bool okk[FOR_ROWS_AHEAD];
+#pragma unroll
+            for (uint32_t k = 0; k < FOR_ROWS_AHEAD; ++k) {
+                const uint32_t t0 = g0 + 64u * k;
+                vv[k] = 0u;
+                ee[k] = 0u;
+                okk[k] = false;
+                if (t0 < total) {  // wave-uniform
+                    wave_sync();   // the previous chunk's reads of MK are done
+                    MK[l] = 0u;
+                    if (len && excl >= t0 && excl - t0 < 64u) MK[excl - t0] = l + 1u;
+                    wave_sync();  // other lanes' marks are visible
+                    uint32_t own = MK[l];
+                    VC_DPP_SCAN(own, op_max, 0u);
+                    own = own > carry ? own : carry;
+                    carry = __builtin_amdgcn_readlane(own, 63);
+                    const uint32_t j = own - 1u;
+                    const uint32_t t = t0 + l;
+                    okk[k] = t < total;
+                    vv[k] = shfl(v, j);
+                    ee[k] = t + shfl(delta, j);
+                }
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < FOR_ROWS_AHEAD; ++k) ww[k] = okk[k] ? col(ee[k]) : 0u;
+#pragma unroll
+            for (uint32_t k = 0; k < FOR_ROWS_AHEAD; ++k)
+                if (g0 + 64u * k < total) f(okk[k], vv[k], ww[k]);
         }
     }
 }
 
-template <typename D>
+// slot header word 7
+constexpr uint32_t SLOT_COUNTED = 1u;  // the node holds a LiveNodes count of its scope
+constexpr uint32_t SLOT_INDUCE = 2u;   // first node of a component child: induce its subgraph
+
+template <typename D, bool HL>
 struct Worker {
     using DG = Deg<D>;
     SearchArgs A;
@@ -111,6 +134,7 @@ struct Worker {
     uint64_t key;   // max over live v of (deg << 32 | ~v): v_max, lowest id on ties
     bool known_connected;
     bool small_off;  // this node goes through the general path (after a split)
+    bool induce_first;  // the fetched node is a component child's first node
     uint64_t *ADJ, *SM;  // small-node solver: adjacency masks, stack masks
     uint32_t* SS;        // and stack counts
     // worker state
@@ -133,9 +157,11 @@ struct Worker {
 
     __device__ __forceinline__ Worker(const SearchArgs& a, uint8_t* lds) : A(a) {
         deg = reinterpret_cast<D*>(lds);
-        L = reinterpret_cast<uint32_t*>(lds + a.lds_L);
-        Q = reinterpret_cast<uint32_t*>(lds + a.lds_Q);
-        R = reinterpret_cast<uint32_t*>(lds + a.lds_R);
+        // the lists: LDS, or this worker's region of HBM
+        uint8_t* lb = HL ? a.hl_base + (size_t)blockIdx.x * a.hl_stride : lds;
+        L = reinterpret_cast<uint32_t*>(lb + a.lds_L);
+        Q = reinterpret_cast<uint32_t*>(lb + a.lds_Q);
+        R = reinterpret_cast<uint32_t*>(lb + a.lds_R);
         VB = reinterpret_cast<uint32_t*>(lds + a.lds_VB);
         PB = reinterpret_cast<uint32_t*>(lds + a.lds_PB);
         MK = reinterpret_cast<uint32_t*>(lds + a.lds_MK);
@@ -158,11 +184,20 @@ struct Worker {
         c_queued = 0;
         nodes = cbr = comps = dons = pushes = lviews = nodes_flushed = 0;
         known_connected = false;
+        induce_first = false;
         view = -1;
         vn = vpad = vbw = 0;
         vlds = false;
         goff = gcol = nullptr;
         GC = G;
+    }
+
+    // Order the lanes' list traffic: LDS as wave_sync does; with the lists
+    // in HBM, every memory operation of the wave is also complete first, so
+    // a lane reads what another lane stored before this point.
+    __device__ __forceinline__ void wsync() {
+        if (HL) order_point();
+        wave_sync();
     }
 
     // charge the shader cycles since the last mark to activity k
@@ -229,6 +264,7 @@ struct Worker {
         st_relaxed(&r->g_nnz, g_nnz);
         st_relaxed(&r->att, 0);
         st_relaxed(&r->unatt, 0);
+        st_relaxed(&r->done, 0);
     }
 
     // ------------------------------------------------------- graph views
@@ -251,7 +287,7 @@ struct Worker {
             const uint32_t words = n + 1u + nnz;
             if (words <= A.gcache_words) {
                 for (uint32_t i = lane(); i < words; i += 64) G[i] = ld_coh(&src[i]);
-                wave_sync();
+                wsync();
                 vlds = true;
                 GC = G + n + 1u;
             } else {
@@ -296,7 +332,7 @@ struct Worker {
             cnt += popc(m);
         }
         nl = cnt;
-        wave_sync();
+        wsync();
     }
 
     // drop the vertices of L that are no longer live (order kept)
@@ -312,12 +348,12 @@ struct Worker {
             const uint32_t v = i < nl ? L[i] : 0u;
             const bool lv = i < nl && DG::live(DG::get(deg, v));
             const uint64_t m = ballot(lv);
-            wave_sync();  // every lane has read its entry before any moves
+            wsync();  // every lane has read its entry before any moves
             if (lv) L[cnt + mbcnt(m)] = v;
             cnt += popc(m);
         }
         nl = cnt;
-        wave_sync();
+        wsync();
     }
 
     // Put the vertices of list[0..cnt) into the cover (duplicates allowed):
@@ -333,12 +369,12 @@ struct Worker {
             if (isnew) list[nn + mbcnt(m)] = v;
             nn += popc(m);
         }
-        wave_sync();
+        wsync();
         for_rows([&](uint32_t x) { return vo(x); }, [&](uint32_t e) { return vc(e); }, list, nn, MK,
                  [&](bool ok, uint32_t, uint32_t w) {
             if (ok && DG::live(DG::get(deg, w))) DG::dec(deg, w);
         });
-        wave_sync();
+        wsync();
         s += (int)nn;
         return nn;
     }
@@ -431,7 +467,7 @@ struct Worker {
                     k = kk > k ? kk : k;
                 }
             }
-            wave_sync();
+            wsync();
             // 2|E| and the branching key of the current live set (final
             // once a round applies no rule)
             e2 = wave_sum(dsum);
@@ -469,7 +505,7 @@ struct Worker {
                 if (add_w) R[cnt + mbcnt(m2)] = w;
                 cnt += popc(m2);
             }
-            wave_sync();
+            wsync();
             if (cnt) {
                 take_list(R, cnt);
                 recompact();
@@ -494,7 +530,7 @@ struct Worker {
             VB[i] = 0u;
             PB[i] = 0u;
         }
-        wave_sync();
+        wsync();
         uint32_t qn = 0, nc = 0, sp = 0;
         while (qn < nl) {
             uint32_t seed = NONE;
@@ -517,7 +553,7 @@ struct Worker {
                 Q[qn] = seed;
             }
             ++qn;
-            wave_sync();
+            wsync();
             uint32_t fa = qn - 1, fb = qn, level = 0;
             while (fa < fb) {
                 const bool odd = ((level + 1u) & 1u) != 0u;
@@ -534,7 +570,7 @@ struct Worker {
                     if (nw) Q[qn + mbcnt(m)] = w;
                     qn += popc(m);
                 });
-                wave_sync();
+                wsync();
                 fa = fb;
                 fb = qn;
                 ++level;
@@ -542,7 +578,7 @@ struct Worker {
             }
         }
         R[nc] = qn;
-        wave_sync();
+        wsync();
         return nc;
     }
 
@@ -552,7 +588,8 @@ struct Worker {
     // trailer.  Worklist slots (coh) use coherent stores; private stack
     // slots are written and read by this worker only and use plain stores.
     __device__ __forceinline__ void write_slot(uint8_t* slot, int ss, int sc, uint32_t bv, uint32_t live,
-                               uint32_t stamp, const D* src, int vw, uint32_t npad, bool coh) {
+                               uint32_t stamp, const D* src, int vw, uint32_t npad, bool coh,
+                               uint32_t carried = 1u) {
         const uint32_t l = lane();
         uint32_t hw = 0;  // header word l (8 words)
         if (l == 0) hw = (uint32_t)ss;
@@ -562,6 +599,7 @@ struct Worker {
         if (l == 4) hw = stamp;
         if (l == 5) hw = (uint32_t)vw;
         if (l == 6) hw = inst;
+        if (l == 7) hw = carried;
         uint32_t* h = reinterpret_cast<uint32_t*>(slot);
         uint32_t* tr = reinterpret_cast<uint32_t*>(slot + A.slot_bytes - 16u);
         const uint32_t nw = (npad * (uint32_t)sizeof(D)) / 8u;
@@ -587,13 +625,14 @@ struct Worker {
         s = uni((int)shfl(hw, 0));
         scope = uni((int)shfl(hw, 1));
         const uint32_t bv = uni(shfl(hw, 2));
+        induce_first = (uni(shfl(hw, 7)) & SLOT_INDUCE) != 0u;
         set_inst(uni(shfl(hw, 6)));
         load_view(uni((int)shfl(hw, 5)));
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(slot + sizeof(SlotHdr));
         uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
         const uint32_t nw = (vpad * (uint32_t)sizeof(D)) / 8u;
         for (uint32_t i = l; i < nw; i += 64) d8[i] = s8[i];
-        wave_sync();
+        wsync();
         return bv;
     }
 
@@ -619,22 +658,86 @@ struct Worker {
         s = uni((int)shfl(hw, 0));
         scope = (int)sc;
         bv = uni(shfl(hw, 2));
+        induce_first = (uni(shfl(hw, 7)) & SLOT_INDUCE) != 0u;
         set_inst(ins);
         load_view((int)vw);
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(slot + sizeof(SlotHdr));
         uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
         const uint32_t nw = (vpad * (uint32_t)sizeof(D)) / 8u;
         for (uint32_t i = l; i < nw; i += 64) d8[i] = ld_coh64(&s8[i]);
-        wave_sync();
+        wsync();
         return true;
     }
 
-    // start on a node copied into LDS: live list, then the pending N(v)
+    // start on a node copied into LDS: live list, then the pending N(v); the
+    // first node of a component child registered without its own subgraph
+    // induces it here (so the children of one branch are induced by the
+    // workers that take them, in parallel)
     __device__ __forceinline__ void begin_node(uint32_t bv) {
         build_live();
         known_connected = false;
         small_off = false;
+        if (induce_first) {
+            induce_first = false;
+            adopt_component_view();
+            known_connected = true;  // a component, as registered
+        }
         if (bv != NONE) take_neighbours(bv);
+    }
+
+    // The node holds exactly its scope's component, in the ids of the view
+    // it was found in.  Induce the component as a subgraph of its own (local
+    // ids = positions in the live list), make it the entry's view, rewrite
+    // the entry's initial cover in local ids (under its lock: a parent may be
+    // reading the children's covers), and move the degree array to local ids.
+    __device__ __forceinline__ void adopt_component_view() {
+        const uint32_t l = lane();
+        const uint32_t size = nl;
+        uint32_t dsum = 0;
+        for (uint32_t i = l; i < size; i += 64) dsum += DG::get(deg, L[i]);
+        const uint32_t nnz = wave_sum(dsum);
+        if (size < 2u || size + 1u + nnz > A.gcache_words || size >= vn) return;
+        for (uint32_t i = l; i < size; i += 64) Q[i] = L[i];
+        wsync();
+        const int e = scope;
+        lock(e);
+        const uint32_t g_at = induce_component(0, size, nnz, R + A.n_pad + 64u, L);
+        if (g_at != NONE) {
+            const int cs = reg_field(&A.reg[e].cover_size);
+            if (cs == (int)size - 1) {
+                uint32_t* bm = bitmap(e);
+                const uint32_t w = (size + 31u) / 32u;
+                for (uint32_t i = l; i < w; i += 64) {
+                    uint32_t bits = ~0u;
+                    if (i == w - 1u && (size & 31u)) bits = (1u << (size & 31u)) - 1u;
+                    if (i == 0) bits &= ~1u;  // all but local vertex 0
+                    st_coh(&bm[i], bits);
+                }
+            }
+            if (l == 0) {
+                st_relaxed(&A.reg[e].view, e);
+                st_relaxed(&A.reg[e].vn, (int)size);
+                st_relaxed(reinterpret_cast<int*>(&A.reg[e].g_at), (int)g_at);
+                st_relaxed(&A.reg[e].g_nnz, (int)nnz);
+            }
+            ++lviews;
+        }
+        unlock(e);
+        if (g_at == NONE) {
+            build_live();  // L was the induction's scratch
+            return;
+        }
+        // degrees in local ids: position i of Q
+        const uint32_t cpad = (size + 63u) & ~63u;
+        D* cd = reinterpret_cast<D*>(R);
+        for (uint32_t i = l; i < cpad; i += 64) DG::set(cd, i, i < size ? DG::get(deg, Q[i]) : 0u);
+        wsync();
+        const uint64_t* s8 = reinterpret_cast<const uint64_t*>(cd);
+        uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
+        for (uint32_t i = l; i < (cpad * (uint32_t)sizeof(D)) / 8u; i += 64) d8[i] = s8[i];
+        wsync();
+        load_view(e);
+        build_live();
     }
 
     // the N(v) branch: every live neighbour of v goes into the cover
@@ -650,7 +753,7 @@ struct Worker {
             if (lv) R[cnt + mbcnt(m)] = w;
             cnt += popc(m);
         }
-        wave_sync();
+        wsync();
         take_list(R, cnt);
         recompact();
     }
@@ -695,7 +798,7 @@ struct Worker {
 
     __device__ __forceinline__ void wl_publish(uint64_t pos) {
         ++c_queued;  // until the next poll
-        wave_sync();
+        wsync();
         if (lane() == 0) {
             add_relaxed(&A.ctl->outstanding, 1);
             publish_order();
@@ -730,7 +833,7 @@ struct Worker {
         }
         res = uni(res);
         if (res == ~0ull) return false;
-        wave_sync();
+        wsync();
         const uint8_t* slot = A.wl_slots + (size_t)(res % A.wl_cap) * A.slot_bytes;
         const uint32_t want = (uint32_t)res;
         uint32_t bv = NONE;
@@ -741,7 +844,7 @@ struct Worker {
                 if (tries == 0) add_relaxed(&A.ctl->stale, 1ull);
                 fence_acquire();
             }
-            wave_sync();
+            wsync();
             fresh = copy_slot_coh(slot, want, bv);
         }
         if (!fresh) {
@@ -817,6 +920,12 @@ struct Worker {
         uint32_t hw = l < 8 ? h[l] : 0u;
         if (l == 4) hw = stamp;
         const uint32_t vw = uni(shfl(hw, 5));
+        // a node leaving the worker takes a count of its own (nodes in the
+        // worklist always carry one)
+        const int bsc = (int)uni(shfl(hw, 1));
+        if ((uni(shfl(hw, 7)) & SLOT_COUNTED) == 0u && counted(bsc) && l == 0)
+            add_relaxed(&A.reg[bsc].live, 1);
+        if (l == 7) hw |= SLOT_COUNTED;
         // the entry's view decides how much of the degree array is in use
         const uint32_t n = view_n((int)vw);
         const uint32_t npad = (n + 63u) & ~63u;
@@ -847,10 +956,10 @@ struct Worker {
             uint32_t spins = 0;
             while (!cas_acquire(&A.reg[e].lock, 0, 1)) backoff(spins);
         }
-        wave_sync();
+        wsync();
     }
     __device__ __forceinline__ void unlock(int e) {
-        wave_sync();
+        wsync();
         if (lane() == 0) {
             publish_order();
             st_relaxed(&A.reg[e].lock, 0);
@@ -938,7 +1047,7 @@ struct Worker {
                 const uint32_t ebw = ((uint32_t)reg_field(&A.reg[e].vn) + 31u) / 32u;
                 const int nch = reg_field(&A.reg[from].nchild);
                 for (uint32_t wi = l; wi < ebw; wi += 64) VB[wi] = ld_coh(&bitmap(from)[wi]);
-                wave_sync();
+                wsync();
                 for (int c = from + 1; c <= from + nch; ++c) {
                     // in PVC the children may still be improving: read each
                     // child's cover under its lock (ancestor locks are always
@@ -964,12 +1073,12 @@ struct Worker {
                             if (x) atomicOr(&VB[wi], x);
                         }
                     }
-                    wave_sync();
+                    wsync();
                     if (pvc) unlock(c);
                 }
                 for (uint32_t wi = l; wi < ebw; wi += 64) st_coh(&dst[wi], VB[wi]);
             }
-            wave_sync();
+            wsync();
             if (lane() == 0) st_relaxed(&A.reg[e].cover_size, val);
             b_reg += 4ull * vbw;
             wrote = true;
@@ -1003,7 +1112,58 @@ struct Worker {
     __device__ __forceinline__ bool counted(int e) { return A.batch || e != 0; }
     __device__ __forceinline__ bool is_root(int e) { return e < (int)A.n_roots; }
 
+    // LiveNodes (Sec. III-C) counts the nodes of a scope, but a worker keeps
+    // the count of a chain of its own nodes as one: a child pushed on the
+    // private stack carries no count (header word 7 = 0) while the node that
+    // pushed it runs, and when a counted node of scope e finishes with an
+    // uncounted node of scope e on top of its stack, the count passes to
+    // that node instead of being decremented.  A node that leaves the worker
+    // (donation, the worklist) takes a count of its own, and so does the top
+    // uncounted node when the current node stops being in scope e (a branch
+    // on components).  So the counter is zero exactly when no node of the
+    // scope is left, with atomics only where work crosses workers or scopes.
+    __device__ __forceinline__ uint32_t count_child(int sc, bool leaves) {
+        if (!counted(sc)) return 1u;
+        if (!leaves) return 0u;
+        if (lane() == 0) add_relaxed(&A.reg[sc].live, 1);
+        return 1u;
+    }
+
+    // the top slot of the private stack, if it is an uncounted node of scope
+    // e (its header), else null
+    __device__ __forceinline__ uint32_t* uncounted_top(int e) {
+        if (top <= bot) return nullptr;
+        uint32_t* h = reinterpret_cast<uint32_t*>(stack + (size_t)(top - 1u) * A.slot_bytes);
+        uint32_t sc = 0, ca = SLOT_COUNTED;
+        if (lane() == 0) {
+            sc = h[1];
+            ca = h[7];
+        }
+        return ((int)uni(sc) == e && (uni(ca) & SLOT_COUNTED) == 0u) ? h : nullptr;
+    }
+
+    // the current node (scope e) goes on in another scope: the uncounted
+    // node it would have handed its count to gets one of its own
+    __device__ __forceinline__ void settle_count(int e) {
+        if (!counted(e)) return;
+        uint32_t* h = uncounted_top(e);
+        if (!h) return;
+        if (lane() == 0) {
+            add_relaxed(&A.reg[e].live, 1);
+            h[7] |= SLOT_COUNTED;
+        }
+        wsync();
+    }
+
     __device__ __forceinline__ void complete(int e) {
+        if (counted(e)) {
+            uint32_t* h = uncounted_top(e);
+            if (h) {
+                if (lane() == 0) h[7] |= SLOT_COUNTED;  // the count passes down the stack
+                wsync();
+                return;
+            }
+        }
         for (;;) {
             if (is_root(e)) {
                 if (A.batch) {
@@ -1024,7 +1184,9 @@ struct Worker {
             if (lane() == 0) old = add_relaxed(&A.reg[e].live, -1);
             old = uni(old);
             if (old != 1) return;
+            const bool audit = (A.flags & VC_OPT_CHECK_REGISTRY) != 0;
             if (lane() == 0 && A.strong_fences) fence_acquire();
+            if (lane() == 0 && audit) add_relaxed(&A.reg[e].done, 1);
             const int p = reg_field(&A.reg[e].up);
             const int cb = reg_field(&A.reg[e].best);
             if (lane() == 0) {
@@ -1035,7 +1197,8 @@ struct Worker {
             old = uni(old);
             if (old != 1) return;
             if (lane() == 0 && A.strong_fences) fence_acquire();
-            wave_sync();
+            if (lane() == 0 && audit) add_relaxed(&A.reg[p].done, 1);
+            wsync();
             const int sum = reg_field(&A.reg[p].best);
             const int a = reg_field(&A.reg[p].up);
             improve(a, sum, p);
@@ -1092,14 +1255,13 @@ struct Worker {
     // current state plus v), the G - v child continues here
     __device__ __forceinline__ bool vertex_branch() {
         const uint32_t v = ~(uint32_t)(key & 0xFFFFFFFFull);
-        if (counted(scope) && lane() == 0) add_relaxed(&A.reg[scope].live, 1);
         const int ss = s, sc = scope;
         if (!push_node(nl, [&](uint8_t* slot, uint32_t stamp, bool coh) {
-                write_slot(slot, ss, sc, v, nl, stamp, deg, view, vpad, coh);
+                write_slot(slot, ss, sc, v, nl, stamp, deg, view, vpad, coh, count_child(sc, coh));
             }))
             return false;
         if (lane() == 0) R[0] = v;
-        wave_sync();
+        wsync();
         take_list(R, 1);
         recompact();
         known_connected = false;  // removing v may split the graph
@@ -1146,7 +1308,7 @@ struct Worker {
                 if (l == 0) NT[nt] = c;
                 ++nt;
             }
-            wave_sync();
+            wsync();
         }
         return nt;
     }
@@ -1190,7 +1352,7 @@ struct Worker {
             carry += shfl(incl, 63);
         }
         if (l == 0) st_coh(&g[size], carry);
-        wave_sync();
+        wsync();
         // columns: the component's rows spread over the lanes (for_rows);
         // each live entry takes the next place of its row (CUR: row cursors,
         // so the order inside a row is arbitrary)
@@ -1198,11 +1360,12 @@ struct Worker {
         for_rows([&](uint32_t x) { return vo(x); }, [&](uint32_t e) { return vc(e); }, Q + a, size,
                  MK, [&](bool ok, uint32_t x, uint32_t w) {
                      if (ok && DG::live(DG::get(deg, w))) {
-                         const uint32_t pos = atomicAdd(&CUR[M[x]], 1u);
+                         const uint32_t pos = __hip_atomic_fetch_add(
+                             &CUR[M[x]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                          st_coh(&gc[pos], M[w]);
                      }
                  });
-        wave_sync();
+        wsync();
         return (uint32_t)at;
     }
 
@@ -1238,6 +1401,7 @@ struct Worker {
         }
         p = uni(p);
         if (p == NONE) return CB_FULL;
+        settle_count(scope);
         if (l == 0) init_entry((int)p, base_sum, (int)nt, scope, INF, (int)nt, 0, view, (int)vn, 0u, 0);
         write_in_bitmap(bitmap((int)p));
         b_reg += (uint64_t)(nt + 1u) * sizeof(RegEntry) + 4ull * vbw * (nt + 1u);
@@ -1254,7 +1418,10 @@ struct Worker {
             const uint32_t nnz = wave_sum(dsum);
             const int e = (int)(p + 1u + j);
             uint32_t g_at = NONE;
-            if (size + 1u + nnz <= A.gcache_words && size < vn) g_at = induce_component(a, b, nnz, M, L);
+            // child 0 continues here and gets its own subgraph now; the
+            // others get theirs from the worker that starts them
+            if (j == 0 && size + 1u + nnz <= A.gcache_words && size < vn)
+                g_at = induce_component(a, b, nnz, M, L);
             const bool own = g_at != NONE;
             if (l == 0)
                 init_entry(e, bi, 1, (int)p, attained ? (int)size - 1 : INF, 0, (int)size,
@@ -1272,12 +1439,12 @@ struct Worker {
                     }
                 } else {
                     for (uint32_t i = l; i < vbw; i += 64) VB[i] = 0u;
-                    wave_sync();
+                    wsync();
                     for (uint32_t i = a + 1u + l; i < b; i += 64) {
                         uint32_t v = Q[i];
                         atomicOr(&VB[v >> 5], 1u << (v & 31u));
                     }
-                    wave_sync();
+                    wsync();
                     for (uint32_t i = l; i < vbw; i += 64) st_coh(&bm[i], VB[i]);
                 }
             }
@@ -1286,7 +1453,7 @@ struct Worker {
                 if (attained) add_relaxed(&A.reg[p].att, (int)size - 1);
                 else add_relaxed(&A.reg[p].unatt, 1);
             }
-            wave_sync();
+            wsync();
         }
         if (l == 0) add_relaxed(&A.reg[p].att, base_sum);
         // entries, covers and graphs are complete before any child can run
@@ -1306,16 +1473,17 @@ struct Worker {
                 uint4* z = reinterpret_cast<uint4*>(cd);
                 const uint32_t nv = (cpad * (uint32_t)sizeof(D)) / 16u;
                 for (uint32_t i = l; i < nv; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
-                wave_sync();
+                wsync();
                 for (uint32_t i = a + l; i < b; i += 64) {
                     uint32_t v = Q[i];
                     cd[own ? i - a : v] = (D)DG::get(deg, v);
                 }
-                wave_sync();
+                wsync();
             }
             const int vw = own ? e : view;
+            const uint32_t flags = SLOT_COUNTED | (own ? 0u : SLOT_INDUCE);
             bool ok = push_node(size, [&](uint8_t* slot, uint32_t stamp, bool coh) {
-                write_slot(slot, 0, e, NONE, size, stamp, cd, vw, cpad, coh);
+                write_slot(slot, 0, e, NONE, size, stamp, cd, vw, cpad, coh, flags);
             });
             if (!ok) return CB_OK;  // error flagged; the next node stops
         }
@@ -1330,25 +1498,25 @@ struct Worker {
                 uint4* z = reinterpret_cast<uint4*>(cd);
                 const uint32_t nv = (cpad * (uint32_t)sizeof(D)) / 16u;
                 for (uint32_t i = l; i < nv; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
-                wave_sync();
+                wsync();
                 for (uint32_t i = a + l; i < b; i += 64) cd[i - a] = (D)DG::get(deg, Q[i]);
-                wave_sync();
+                wsync();
                 const uint64_t* s8 = reinterpret_cast<const uint64_t*>(cd);
                 uint64_t* d8 = reinterpret_cast<uint64_t*>(deg);
                 for (uint32_t i = l; i < (cpad * (uint32_t)sizeof(D)) / 8u; i += 64) d8[i] = s8[i];
-                wave_sync();
+                wsync();
                 load_view(e);
             } else {
                 for (uint32_t i = l; i < vbw; i += 64) VB[i] = 0u;
-                wave_sync();
+                wsync();
                 for (uint32_t i = a + l; i < b; i += 64) {
                     uint32_t v = Q[i];
                     atomicOr(&VB[v >> 5], 1u << (v & 31u));
                 }
-                wave_sync();
+                wsync();
                 for (uint32_t v = l; v < vn; v += 64)
                     if (!((VB[v >> 5] >> (v & 31u)) & 1u)) DG::set(deg, v, 0u);
-                wave_sync();
+                wsync();
             }
             s = 0;
             scope = e;
@@ -1400,12 +1568,12 @@ struct Worker {
 #pragma unroll
         for (int k = 0; k < W; ++k)
             if (mine[k] && ((tin[k] >> lane()) & 1ull)) DG::set(deg, vid[k], DG::IN);
-        wave_sync();
+        wsync();
         improve(scope, val, -1);
 #pragma unroll
         for (int k = 0; k < W; ++k)
             if (mine[k]) DG::set(deg, vid[k], d0[k]);
-        wave_sync();
+        wsync();
         if (val < best) best = val;
     }
 
@@ -1443,24 +1611,23 @@ struct Worker {
         const uint64_t* s8 = reinterpret_cast<const uint64_t*>(deg);
         uint64_t* d8 = reinterpret_cast<uint64_t*>(cd);
         for (uint32_t i = l; i < (vpad * (uint32_t)sizeof(D)) / 8u; i += 64) d8[i] = s8[i];
-        wave_sync();
+        wsync();
 #pragma unroll
         for (int k = 0; k < W; ++k)
             if (mine[k]) DG::set(cd, vid[k], small_entry<W>(adj, lv, ti, k, l));
-        wave_sync();
+        wsync();
         uint32_t live = 0;
 #pragma unroll
         for (int j = 0; j < W; ++j) live += popc64(lv[j]);
-        if (counted(scope) && lane() == 0) add_relaxed(&A.reg[scope].live, 1);
         const int ss = sv, sc = scope;
         if (donate) {
             write_slot(A.wl_slots + (size_t)(pos % A.wl_cap) * A.slot_bytes, ss, sc, NONE, live,
-                       (uint32_t)pos, cd, view, vpad, true);
+                       (uint32_t)pos, cd, view, vpad, true, count_child(sc, true));
             wl_publish(pos);
             return true;
         }
         return push_node(live, [&](uint8_t* slot, uint32_t stamp, bool coh) {
-            write_slot(slot, ss, sc, NONE, live, stamp, cd, view, vpad, coh);
+            write_slot(slot, ss, sc, NONE, live, stamp, cd, view, vpad, coh, count_child(sc, coh));
         });
     }
 
@@ -1480,7 +1647,7 @@ struct Worker {
             d0[k] = mine[k] ? DG::get(deg, vid[k]) : 0u;
             if (mine[k]) P[vid[k]] = p;
         }
-        wave_sync();
+        wsync();
         uint64_t adj[W][W];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -1499,7 +1666,7 @@ struct Worker {
 #pragma unroll
             for (int j = 0; j < W; ++j) ADJ[(l + 64u * k) * W + j] = adj[k][j];
         }
-        wave_sync();
+        wsync();
         const int s0 = s;
         uint64_t live[W], tin[W];
 #pragma unroll
@@ -1774,7 +1941,7 @@ struct Worker {
 #pragma unroll
                     for (int k = 0; k < W; ++k)
                         if (mine[k]) DG::set(deg, vid[k], small_entry<W>(adj, live, tin, k, l));
-                    wave_sync();
+                    wsync();
                     s = s0 + sl;
                     recompact();
                     return SMALL_SPLIT;
@@ -1801,7 +1968,7 @@ struct Worker {
                     for (uint32_t i = l; i < cnt * 2u * W; i += 64)
                         SM[i] = SM[(uint32_t)bot * 2u * W + i];
                     for (uint32_t i = l; i < cnt; i += 64) SS[i] = SS[(uint32_t)bot + i];
-                    wave_sync();
+                    wsync();
                     top = (int)cnt;
                     bot = 0;
                 }
@@ -1827,7 +1994,7 @@ struct Worker {
                     }
                     SS[top] = (uint32_t)(sl + (int)cnb);
                 }
-                wave_sync();
+                wsync();
                 ++top;
                 live[v >> 6] &= ~(1ull << (v & 63u));
                 tin[v >> 6] |= 1ull << (v & 63u);
@@ -1998,11 +2165,38 @@ struct Worker {
         load_view((int)got);
         for (uint32_t v = lane(); v < vpad; v += 64)
             DG::set(deg, v, v < vn ? vo(v + 1) - vo(v) : 0u);
-        wave_sync();
+        wsync();
         s = 0;
         scope = (int)got;
         begin_node(NONE);
+        if (!A.serve) greedy_bound();
         return true;
+    }
+
+    // A batch instance's initial bound (Sec. II-B: an attained cover such as
+    // a greedy one).  From the instance's root node, the degree rules run to
+    // their fixpoint and a maximum-degree vertex (lowest id on ties) goes
+    // into the cover, repeatedly, until no edge is left; the vertices taken
+    // (by the rules and by the greedy choices) form a cover, offered as the
+    // root's Best.  A PVC query within k is answered by it at once.  The root
+    // node waits meanwhile in the (empty) private stack's first slot and is
+    // then restored, so the search starts from it with the high-degree rule
+    // under the new bound.
+    __device__ __forceinline__ void greedy_bound() {
+        uint8_t* keep = stack + (size_t)top * A.slot_bytes;
+        write_slot(keep, s, scope, NONE, nl, 0u, deg, view, vpad, false);
+        best = INF;  // no bound yet: the degree rules alone
+        for (;;) {
+            reduce();
+            if (e2 == 0) break;
+            if (lane() == 0) R[0] = ~(uint32_t)(key & 0xFFFFFFFFull);
+            wsync();
+            take_list(R, 1);
+            recompact();
+        }
+        improve(scope, s, -1);
+        begin_node(copy_slot(keep));
+        charge(CYC_REDUCE);
     }
 
     __device__ __forceinline__ void run() {
@@ -2107,10 +2301,10 @@ struct Worker {
     }
 };
 
-template <typename D>
+template <typename D, bool HL>
 __global__ void __launch_bounds__(64) search_kernel(SearchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    Worker<D> w(a, lds);
+    Worker<D, HL> w(a, lds);
     w.run();
 }
 
@@ -2161,15 +2355,15 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
     }
 }
 
-template <typename D>
+template <typename D, bool HL>
 hipError_t launch_t(const SearchArgs& a, uint32_t workers, hipStream_t st) {
-    hipLaunchKernelGGL(search_kernel<D>, dim3(workers), dim3(64), a.lds_bytes, st, a);
+    hipLaunchKernelGGL((search_kernel<D, HL>), dim3(workers), dim3(64), a.lds_bytes, st, a);
     return hipGetLastError();
 }
 
-template <typename D>
+template <typename D, bool HL>
 hipError_t occ_t(uint32_t lds_bytes, int* bpc) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, search_kernel<D>, 64, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, search_kernel<D, HL>, 64, lds_bytes);
 }
 
 template <typename D>

@@ -123,6 +123,12 @@ struct Server {
     std::vector<int> h_state;
     std::vector<uint64_t> h_nodes;
 
+    std::vector<DevBuf*> buffers() {
+        return {&in_off, &in_col, &rdeg,   &gdeg,     &gin,    &addf,  &newly, &flags,
+                &newid,  &oldid,  &kdeg,   &koff,     &kcol,   &cover, &scan_tmp, &ctr,
+                &hsum,   &pool,   &stacks, &wl_slots, &wl_seq, &ctl,   &reg,   &bitmaps,
+                &arena,  &st,     &nodes,  &kk,       &cancel};
+    }
     vc_status plan();
     vc_status root_bufs(uint64_t n, uint64_t nnz, RootBufs* b);
     vc_status open_resident();
@@ -201,19 +207,20 @@ vc_status Server::plan() {
     a.n_roots = slots;
     a.batch = 1;
     a.serve = 1;
+    a.strong_fences = (c->opts.flags & VC_OPT_STRONG_ORDER) ? 1u : 0u;
     a.inst_node_limit = c->opts.node_limit;
-    HIPCHK(ensure(stacks, (size_t)workers * depth * slot_bytes));
-    HIPCHK(ensure(wl_slots, (size_t)wl_cap * slot_bytes));
-    HIPCHK(ensure(wl_seq, 8ull * wl_cap));
-    HIPCHK(ensure(ctl, sizeof(Ctl)));
-    HIPCHK(ensure(reg, sizeof(RegEntry) * reg_cap));
-    HIPCHK(ensure(bitmaps, 4ull * bm_words * reg_cap));
-    HIPCHK(ensure(arena, 4ull * arena_words));
-    HIPCHK(ensure(st, 4ull * slots));
-    HIPCHK(ensure(nodes, 8ull * slots));
-    HIPCHK(ensure(kk, 4ull * slots));
-    HIPCHK(ensure(cancel, 4ull * slots));
-    HIPCHK(ensure(pool, 4ull * pool_cap));
+    HIPCHK(ensure(c->pool, stacks, (size_t)workers * depth * slot_bytes));
+    HIPCHK(ensure(c->pool, wl_slots, (size_t)wl_cap * slot_bytes));
+    HIPCHK(ensure(c->pool, wl_seq, 8ull * wl_cap));
+    HIPCHK(ensure(c->pool, ctl, sizeof(Ctl)));
+    HIPCHK(ensure(c->pool, reg, sizeof(RegEntry) * reg_cap));
+    HIPCHK(ensure(c->pool, bitmaps, 4ull * bm_words * reg_cap));
+    HIPCHK(ensure(c->pool, arena, 4ull * arena_words));
+    HIPCHK(ensure(c->pool, st, 4ull * slots));
+    HIPCHK(ensure(c->pool, nodes, 8ull * slots));
+    HIPCHK(ensure(c->pool, kk, 4ull * slots));
+    HIPCHK(ensure(c->pool, cancel, 4ull * slots));
+    HIPCHK(ensure(c->pool, pool, 4ull * pool_cap));
     a.stacks = (uint8_t*)stacks.p;
     a.wl_slots = (uint8_t*)wl_slots.p;
     a.wl_seq = (uint64_t*)wl_seq.p;
@@ -240,23 +247,23 @@ vc_status Server::root_bufs(uint64_t n, uint64_t nnz, RootBufs* b) {
         n_root = std::max<uint64_t>(n, n_root);
         nnz_root = std::max<uint64_t>(nnz, nnz_root);
         const size_t n1 = n_root + 1;
-        HIPCHK(ensure(in_off, 4 * n1));
-        HIPCHK(ensure(in_col, 4 * std::max<uint64_t>(nnz_root, 1)));
-        HIPCHK(ensure(rdeg, 4 * n1));
-        HIPCHK(ensure(gdeg, 4 * n1));
-        HIPCHK(ensure(gin, n1));
-        HIPCHK(ensure(addf, n1));
-        HIPCHK(ensure(newly, n1));
-        HIPCHK(ensure(flags, 4 * (n1 + 1)));
-        HIPCHK(ensure(newid, 4 * (n1 + 1)));
-        HIPCHK(ensure(oldid, 4 * n1));
-        HIPCHK(ensure(kdeg, 4 * (n1 + 1)));
-        HIPCHK(ensure(koff, 4 * (n1 + 1)));
-        HIPCHK(ensure(kcol, 4 * std::max<uint64_t>(nnz_root, 1)));
-        HIPCHK(ensure(cover, 4 * n1));
-        HIPCHK(ensure(scan_tmp, 4 * (n1 / 2048 + 4)));
-        HIPCHK(ensure(ctr, CTR_COUNT * 4));
-        HIPCHK(ensure(hsum, 8));
+        HIPCHK(ensure(c->pool, in_off, 4 * n1));
+        HIPCHK(ensure(c->pool, in_col, 4 * std::max<uint64_t>(nnz_root, 1)));
+        HIPCHK(ensure(c->pool, rdeg, 4 * n1));
+        HIPCHK(ensure(c->pool, gdeg, 4 * n1));
+        HIPCHK(ensure(c->pool, gin, n1));
+        HIPCHK(ensure(c->pool, addf, n1));
+        HIPCHK(ensure(c->pool, newly, n1));
+        HIPCHK(ensure(c->pool, flags, 4 * (n1 + 1)));
+        HIPCHK(ensure(c->pool, newid, 4 * (n1 + 1)));
+        HIPCHK(ensure(c->pool, oldid, 4 * n1));
+        HIPCHK(ensure(c->pool, kdeg, 4 * (n1 + 1)));
+        HIPCHK(ensure(c->pool, koff, 4 * (n1 + 1)));
+        HIPCHK(ensure(c->pool, kcol, 4 * std::max<uint64_t>(nnz_root, 1)));
+        HIPCHK(ensure(c->pool, cover, 4 * n1));
+        HIPCHK(ensure(c->pool, scan_tmp, 4 * (n1 / 2048 + 4)));
+        HIPCHK(ensure(c->pool, ctr, CTR_COUNT * 4));
+        HIPCHK(ensure(c->pool, hsum, 8));
     }
     b->rdeg = (uint32_t*)rdeg.p;
     b->gdeg = (uint32_t*)gdeg.p;
@@ -710,6 +717,16 @@ void Server::loop() {
     close_resident();
 }
 
+void server_forget_buffers(vc_ctx* c) {
+    Server* s = get_server(c);
+    if (!s) return;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->pending > 0 || s->resident_flag) return;  // callers checked server_busy
+    for (DevBuf* b : s->buffers()) forget(*b);
+    s->planned = false;
+    s->n_root = s->nnz_root = 0;
+}
+
 bool server_busy(vc_ctx* c) {
     Server* s = get_server(c);
     if (!s) return false;
@@ -728,13 +745,7 @@ void server_shutdown(vc_ctx* c) {
         s->cv.notify_all();
     }
     if (s->th.joinable()) s->th.join();
-    DevBuf* bufs[] = {&s->in_off, &s->in_col, &s->rdeg,  &s->gdeg,    &s->gin,     &s->addf,
-                      &s->newly,  &s->flags,  &s->newid, &s->oldid,   &s->kdeg,    &s->koff,
-                      &s->kcol,   &s->cover,  &s->scan_tmp, &s->ctr,  &s->hsum,    &s->pool,
-                      &s->stacks, &s->wl_slots, &s->wl_seq, &s->ctl,  &s->reg,     &s->bitmaps,
-                      &s->arena,  &s->st,     &s->nodes, &s->kk,      &s->cancel};
-    for (DevBuf* b : bufs)
-        if (b->p) hipFree(b->p);
+    for (DevBuf* b : s->buffers()) release(*b);
     if (s->ready) hipEventDestroy(s->ready);
     if (s->ss) hipStreamDestroy(s->ss);
     if (s->ks) hipStreamDestroy(s->ks);

@@ -29,6 +29,8 @@ VC_OPT_NO_INDUCE = 32
 VC_OPT_NO_COMPACT = 64
 VC_OPT_CROWN = 128
 VC_OPT_NO_CROWN = 256
+VC_OPT_STRONG_ORDER = 512
+VC_OPT_CHECK_REGISTRY = 1024
 VC_MIN, VC_PARAM = 0, 1
 
 CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]
@@ -87,7 +89,11 @@ class vc_stats(ctypes.Structure):
                 ("ms_induce", ctypes.c_double), ("ms_search", ctypes.c_double),
                 ("ms_total", ctypes.c_double),
                 ("crown_cover", ctypes.c_uint32), ("crown_removed", ctypes.c_uint32),
-                ("crown_rounds", ctypes.c_uint32)]
+                ("crown_rounds", ctypes.c_uint32),
+                ("stale_reads", ctypes.c_uint64), ("reg_entries", ctypes.c_uint32),
+                ("reg_checked", ctypes.c_uint32), ("reg_open", ctypes.c_uint32),
+                ("reg_parents", ctypes.c_uint32), ("reg_depth", ctypes.c_uint32),
+                ("lists_in_hbm", ctypes.c_uint32)]
 
 
 class VCError(RuntimeError):
@@ -117,8 +123,8 @@ def load():
     p = ctypes.c_void_p
     u32p = ctypes.POINTER(ctypes.c_uint32)
     lib.vc_ctx_create.restype = ctypes.c_int
-    lib.vc_ctx_create.argtypes = [ctypes.c_int, p, ctypes.POINTER(vc_opts),
-                                  ctypes.POINTER(p)]
+    lib.vc_ctx_create.argtypes = [ctypes.c_int, p, p, ctypes.c_uint64,
+                                  ctypes.POINTER(vc_opts), ctypes.POINTER(p)]
     lib.vc_ctx_destroy.restype = ctypes.c_int
     lib.vc_ctx_destroy.argtypes = [p]
     lib.vc_validate.restype = ctypes.c_int
@@ -269,22 +275,38 @@ class Result:
 
 
 class Solver:
-    """One libvc context on a HIP device."""
+    """One libvc context on a HIP device.
+
+    stream: a torch.cuda.Stream or a raw hipStream_t handle; by default
+    PyTorch's current stream on the device (its handle is 0 for the default
+    stream, and the library then orders its own stream after the default
+    one).  arena: optional uint8 device tensor all device buffers are carved
+    from (the library then allocates no device memory); it is kept alive by
+    the Solver."""
 
     def __init__(self, device: int = 0, stream=None, workers: int = 0,
                  donate_slack: int = 0, worklist_cap: int = 0,
                  registry_cap: int = 0, hbm_budget: int = 0,
                  node_limit: int = 0, flags: int = 0, watchdog_ms: int = 0,
                  donate_min: int = 0, gcache_words: int = 0, serve_n_max: int = 0,
-                 serve_slots: int = 0, small_max: int = 0):
+                 serve_slots: int = 0, small_max: int = 0, arena=None):
         lib = load()
         self._opts = vc_opts(workers, donate_slack, worklist_cap, registry_cap,
                              hbm_budget, node_limit, flags, watchdog_ms,
                              donate_min, gcache_words, serve_n_max, serve_slots,
                              small_max)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        handle = getattr(stream, "cuda_stream", stream)
+        self._arena = arena
+        a_ptr, a_bytes = (None, 0)
+        if arena is not None:
+            a_ptr, a_bytes = arena.data_ptr(), arena.numel() * arena.element_size()
         h = ctypes.c_void_p()
-        st = lib.vc_ctx_create(int(device), stream, ctypes.byref(self._opts),
-                               ctypes.byref(h))
+        st = lib.vc_ctx_create(int(device), handle or None, a_ptr, int(a_bytes),
+                               ctypes.byref(self._opts), ctypes.byref(h))
         _check(st, "vc_ctx_create")
         self._h = h
 

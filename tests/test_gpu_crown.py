@@ -98,8 +98,9 @@ def test_crown_equals_no_crown_on_small_graphs(crown_solver, orc):
 
 
 def test_crown_takes_bipartite_union_beyond_lds(libvc):
-    """9,900 vertices that the degree rules leave whole: above the LDS limit
-    of the search, the default (size-gated) crown solves it at the root."""
+    """9,900 vertices that the degree rules leave whole: the default
+    (size-gated) crown solves it at the root; without it the search does,
+    with its lists in HBM."""
     g = bipartite_union(900, 3, 8)
     with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000) as s:
         r = s.mvc(g)
@@ -110,8 +111,11 @@ def test_crown_takes_bipartite_union_beyond_lds(libvc):
         # the last 3 are isolated once H is gone and the degree rules drop them
         assert r.stats["crown_removed"] == 900 * 5
         assert s.pvc(g, 2699).yes is False and s.pvc(g, 2700).yes is True
+    # without the crown the search takes the 9,900-vertex kernel itself, its
+    # lists kept in HBM (they do not fit LDS)
     with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000,
                    flags=vc.VC_OPT_NO_CROWN) as s:
-        with pytest.raises(vc.VCError) as e:
-            s.mvc(g)
-        assert e.value.status == vc.VC_ERANGE
+        r = s.mvc(g)
+        assert r.size == 2700
+        assert_cover(g, r.cover, size=2700)
+        assert r.stats["crown_rounds"] == 0 and r.stats["lists_in_hbm"] == 1

@@ -19,16 +19,27 @@ pytestmark = pytest.mark.gpu
 def solver(libvc):
     import torch
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
-    # a node limit turns a runaway search into a failed test, not a hang
-    s = vc.Solver(0, node_limit=50_000_000, watchdog_ms=60_000)
+    # a node limit turns a runaway search into a failed test, not a hang;
+    # every complete search's registry end state is checked too
+    s = vc.Solver(0, node_limit=50_000_000, watchdog_ms=60_000,
+                  flags=vc.VC_OPT_CHECK_REGISTRY)
     yield s
     s.close()
+
+
+def check_protocol(stats):
+    """No worklist read saw an older payload, and after a search that ran to
+    its end every registry entry was completed exactly once."""
+    assert stats["stale_reads"] == 0, stats
+    if stats["reg_checked"]:
+        assert stats["reg_open"] == 0, stats
 
 
 def gpu_mvc(solver, g, expected):
     r = solver.mvc(g)
     assert r.size == expected, (g.name, r.size, expected)
     assert_cover(g, r.cover, size=expected)
+    check_protocol(r.stats)
     return r
 
 
@@ -38,6 +49,7 @@ def gpu_pvc_threshold(solver, g, mvc, ks=None):
             continue
         r = solver.pvc(g, k)
         assert r.yes == (k >= mvc), (g.name, k, mvc, r.yes)
+        check_protocol(r.stats)
         if r.yes:
             assert_cover(g, r.cover, at_most=k)
         else:

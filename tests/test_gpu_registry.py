@@ -1,0 +1,92 @@
+"""The component branch registry protocol (Sec. III-C, the nested example
+of Fig. 3) checked on the device's own end state.
+
+A graph is built whose first branch on components (the root's, like node 1
+of the figure) has a component that splits again after a branch on its hub
+vertex (node 12 with nodes 13 and 14), three levels deep.  After the search
+the library reads the registry back (VC_OPT_CHECK_REGISTRY): every parent
+and child entry must have been completed exactly once, by the last
+descendant, with every LiveNodes and LiveComps counter back at 0, and the
+nesting must reach the depth the graph forces.  The answers equal the
+oracle's, with one worker (a deterministic order of events) and with all of
+them, with the plain ordering and with agent-scope fences added
+(VC_OPT_STRONG_ORDER); no worklist read may ever see an old payload."""
+import numpy as np
+import pytest
+
+from paper_2512_18334_amd import graphgen as gg
+from paper_2512_18334_amd import vc
+from tests.helpers import assert_cover
+
+pytestmark = pytest.mark.gpu
+
+
+def gadget(level: int):
+    """Level 0: the Petersen graph.  Level L: a hub (vertex 0, the lowest
+    id) joined to three non-hub vertices in each of two level L-1 gadgets.
+    Removing the hub splits it into the two gadgets below."""
+    if level == 0:
+        u, v = gg.petersen().edges()
+        return 10, list(u), list(v), []
+    n1, u1, v1, hubs1 = gadget(level - 1)
+    us, vs, hubs = [], [], [0]
+    base = 1
+    for _ in range(2):
+        us += [x + base for x in u1]
+        vs += [x + base for x in v1]
+        hubs += [h + base for h in hubs1]
+        plain = [x for x in range(n1) if x not in set(hubs1)]
+        for x in plain[:3]:
+            us.append(0)
+            vs.append(x + base)
+        base += n1
+    return base, us, vs, hubs
+
+
+def nested_graph(level: int):
+    n0, u0, v0, _ = gadget(0)
+    n1, u1, v1, _ = gadget(level)
+    u = u0 + [x + n0 for x in u1]
+    v = v0 + [x + n0 for x in v1]
+    return gg.from_edges(n0 + n1, np.array(u), np.array(v), name=f"nested{level}")
+
+
+@pytest.mark.parametrize("level", [1, 2, 3])
+@pytest.mark.parametrize("workers", [1, 0])
+@pytest.mark.parametrize("strong", [False, True])
+def test_nested_component_branches_complete_once(libvc, orc, level, workers, strong):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    g = nested_graph(level)
+    want = orc.mvc(g)["size"]
+    flags = vc.VC_OPT_CHECK_REGISTRY | (vc.VC_OPT_STRONG_ORDER if strong else 0)
+    print(f"registry: level {level} workers {workers} strong {strong} n={g.n}", flush=True)
+    with vc.Solver(0, workers=workers, flags=flags, node_limit=10_000_000,
+                   watchdog_ms=60_000) as s:
+        for _ in range(3):
+            r = s.mvc(g)
+            assert r.size == want
+            assert_cover(g, r.cover, size=want)
+            st = r.stats
+            assert st["reg_checked"] == 1
+            assert st["reg_open"] == 0, st
+            assert st["reg_depth"] >= level + 1, st
+            assert st["reg_parents"] >= level + 1
+            assert st["stale_reads"] == 0
+
+
+@pytest.mark.parametrize("strong", [False, True])
+def test_blocks_and_hubs_registry_end_state(libvc, orc, strong):
+    """The 1,928-vertex blocks-and-hubs graph (MVC 1077, hundreds of branches
+    on components), all workers."""
+    g = gg.config2_blocks_hubs()
+    flags = vc.VC_OPT_CHECK_REGISTRY | (vc.VC_OPT_STRONG_ORDER if strong else 0)
+    with vc.Solver(0, flags=flags, node_limit=50_000_000, watchdog_ms=60_000) as s:
+        for _ in range(3):
+            r = s.mvc(g)
+            assert r.size == 1077
+            assert_cover(g, r.cover, size=1077)
+            st = r.stats
+            assert st["reg_checked"] == 1 and st["reg_open"] == 0, st
+            assert st["reg_parents"] >= 20
+            assert st["stale_reads"] == 0
