@@ -56,9 +56,10 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(per_launch_alg_bytes: float):
-    """HBM bytes per search launch from the committed rocprofv3 counters, or
-    None if they are missing or were taken on a different kernel source."""
+def measured_counters():
+    """The committed rocprofv3 counter figures of the search kernel (HBM
+    bytes, device-scope atomics and waves per launch), or None if they are
+    missing or were taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -66,7 +67,7 @@ def measured_traffic(per_launch_alg_bytes: float):
         return None
     if t.get("kernel_sha") != kernel_source_sha():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t
 
 
 def cpu_baseline(g, budget_s: float):
@@ -85,8 +86,12 @@ def cpu_baseline(g, budget_s: float):
                       f"{el / reps * 1e3:.1f} ms per solve)"}
 
 
+HOST_CORES_MAX = 16  # a one-GPU machine's share of the host's cores
+
+
 def host_info():
-    """The host's CPU model and the cores this process may use."""
+    """The host's CPU model and the cores a CPU pool may use here (the cores
+    this process may run on, at most a one-GPU machine's share)."""
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -100,7 +105,7 @@ def host_info():
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    return model, cores
+    return model, min(cores, HOST_CORES_MAX)
 
 
 def _oracle_batch_instance(i):
@@ -144,10 +149,23 @@ def roofline(stats_list, search_ms):
     cover bitmaps and per-component graphs, all counted on the device) over
     the kernel's time."""
     alg_bytes = sum(2 * s["bytes_nodes"] + s["slot_bytes"] + s["bytes_registry"]
-                    for s in stats_list) / len(stats_list)
+                    + s["bytes_rows"] for s in stats_list) / len(stats_list)
     achieved = alg_bytes / (search_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(alg_bytes)}
+    t = measured_counters()
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS,
+           "traffic": t.get("hbm_bytes_per_launch") if t else None,
+           "alg_bytes_per_launch": alg_bytes}
+    # the secondary view: per-node work is latency and atomic bound
+    s0 = stats_list[-1]
+    out["waves_per_cu"] = s0["workers"] / 256.0
+    if t:
+        if t.get("atomics_per_launch") is not None:
+            out["device_atomics_per_s"] = t["atomics_per_launch"] / (search_ms * 1e-3)
+            out["device_atomics_per_launch"] = t["atomics_per_launch"]
+        if t.get("wave_occupancy") is not None:
+            out["wave_occupancy"] = t["wave_occupancy"]
+    return out
 
 
 def cycle_breakdown(stats):
@@ -220,6 +238,7 @@ def bench_blocks_hubs(args, torch, gg, vc):
                    "tts_host_input_ms_p50": float(np.percentile(host_ms, 50)),
                    "tts_host_input_ms_p90": float(np.percentile(host_ms, 90)),
                    "idle_pct": cycle_breakdown(stats).get("idle", 0.0),
+                   "components_per_branch_hist": s0["comp_hist"],
                    "cycle_breakdown_pct": cycle_breakdown(stats)},
         "roofline": roofline(stats, search_ms),
     }
@@ -624,7 +643,8 @@ def bench_ablation(args, torch, gg, vc):
                             raise
                         hit = True
                         sizes.append(None)
-                    nodes_rep += solver.stats()["tree_nodes"]
+                    solver_stats_last = solver.stats()
+                    nodes_rep += solver_stats_last["tree_nodes"]
                 el = (time.perf_counter() - t0) * 1e3
                 if hit:  # time and nodes up to the limit, once
                     best, nodes = el, nodes_rep
@@ -639,6 +659,14 @@ def bench_ablation(args, torch, gg, vc):
             table.setdefault(wname, {})[aname] = {
                 "ms": round(best, 3), "tree_nodes": nodes,
                 "node_limit_reached": hit}
+            if aname == "proposed":
+                # Table III/IV-style counters of the last solve
+                st = solver_stats_last
+                table[wname][aname].update({
+                    "components_per_branch_hist": st["comp_hist"],
+                    "component_branches": st["component_branches"],
+                    "n_kernel": st["n_kernel"], "max_degree_kernel": st["max_degree_kernel"],
+                    "deg_bytes": st["deg_bytes"], "workers": st["workers"]})
             print(f"ablation {wname} {aname}: {best:.2f} ms, {nodes} nodes"
                   + (" (node limit)" if hit else ""), file=sys.stderr, flush=True)
     p = table["blocks_hubs_n1928"]["proposed"]

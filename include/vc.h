@@ -201,6 +201,13 @@ typedef struct {
     uint32_t lists_in_hbm;       /* 1: the induced subgraph was too large for
                                     the workers' lists in LDS, which were
                                     kept in HBM (Sec. IV-A)                  */
+    uint64_t bytes_rows;         /* CSR bytes (entries and offsets) read from
+                                    HBM-resident views for the rows of the
+                                    vertices the search removed             */
+    uint32_t comp_hist[8];       /* branches on components by the number of
+                                    components registered (Table III): 2,
+                                    3-4, 5-8, 9-16, 17-32, 33-64, 65-128,
+                                    more                                     */
 } vc_stats;
 
 typedef struct vc_ctx vc_ctx;
@@ -236,10 +243,12 @@ vc_status vc_ctx_destroy(vc_ctx *ctx);
 /*
  * Check a CSR graph against the rules stated at vc_csr.  Host arrays are
  * checked exactly on the host and ctx may be NULL; device arrays need a
- * context and are checked by kernels (offsets, ranges, self-loops, repeated
- * entries in sorted rows or unsorted rows of up to 512 entries, symmetry by
- * a 64-bit hash of the unordered pairs).  Returns VC_OK or VC_EINVAL
- * (VC_ERANGE when nnz >= 2^32).
+ * context and are checked by kernels: offsets, ranges, self-loops and
+ * repeated entries exactly; symmetry by a 64-bit signed hash sum over the
+ * unordered pairs, which vanishes for every symmetric graph (an asymmetric
+ * one is accepted only on a hash collision; host input is checked exactly).
+ * The same checks run at the start of every solve of a device graph.
+ * Returns VC_OK or VC_EINVAL (VC_ERANGE when nnz >= 2^32).
  */
 vc_status vc_validate(vc_ctx *ctx, const vc_csr *g);
 

@@ -560,6 +560,8 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         for (int i = 0; i < 6; ++i) stv.cycles[i] = ctl.cyc[i];
         stv.bytes_nodes = ctl.bytes_nodes;
         stv.bytes_registry = ctl.bytes_registry;
+        stv.bytes_rows = ctl.bytes_rows;
+        for (int i = 0; i < 8; ++i) stv.comp_hist[i] = ctl.comp_hist[i];
         stv.slot_bytes = slot_bytes;
         stv.bitmap_bytes = 4u * bm_words;
         float ms = 0;

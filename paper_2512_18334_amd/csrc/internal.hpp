@@ -87,14 +87,17 @@ struct Ctl {
     uint64_t pushes;
     uint64_t stale;   // worklist reads that saw an old payload and re-read
     uint64_t local_views;  // components given their own induced subgraph
-    uint64_t _p5[9];
+    uint32_t comp_hist[8]; // branches on components by number of components
+                           // registered: 2, 3-4, 5-8, 9-16, 17-32, 33-64, 65-128, more
+    uint64_t _p5[5];
     // shader cycles summed over workers, by activity (the time breakdown
     // of Sec. V-D): fetching nodes, rules, component search and
     // registration, vertex branching, registry completion, waiting for work
     uint64_t cyc[6];
     uint64_t bytes_nodes;     // bytes written into node slots (each is read back once)
     uint64_t bytes_registry;  // bytes of registry entries, cover bitmaps and arena graphs written
-    uint64_t _p7[8];
+    uint64_t bytes_rows;      // CSR bytes read from HBM for the rows of removed vertices
+    uint64_t _p7[7];
 };
 enum { CYC_FETCH = 0, CYC_REDUCE, CYC_COMPONENTS, CYC_BRANCH, CYC_COMPLETE, CYC_IDLE };
 

@@ -4,6 +4,8 @@
 // remaining vertices with narrow column ids, and assembling the final cover.
 // These kernels stream the CSR from HBM; each is a grid-stride loop with one
 // vertex per thread.
+#include <algorithm>
+
 #include "dev_common.hpp"
 #include "internal.hpp"
 #include "root.hpp"
@@ -44,6 +46,15 @@ __device__ __forceinline__ void block_atomic_add(uint32_t* p, uint32_t x) {
     }
 }
 
+// LDS of the root-step kernels.  They also run on a served context's side
+// stream beside its resident search, which leaves 32 KB of LDS per CU to
+// them, so none may take more than 16 KB per block (a kernel that could not
+// be placed would wait for the resident search forever); each is launched
+// with 256 threads, which its __launch_bounds__ states.
+constexpr uint32_t SIDE_LDS_MAX = 16384u;
+static_assert(sizeof(uint32_t) * 4u * ROWCHK_TBL <= SIDE_LDS_MAX, "k_check_rows table");
+static_assert(sizeof(uint32_t) * 4u <= SIDE_LDS_MAX, "block_atomic_add partial sums");
+
 #define GRID_LOOP(i, n)                                                        \
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (n);          \
          i += gridDim.x * blockDim.x)
@@ -57,7 +68,7 @@ __device__ __forceinline__ void block_atomic_add(uint32_t* p, uint32_t x) {
 // ------------------------------------------------------------- validation
 
 // offsets: off[0] == 0, non-decreasing, off[n] == nnz
-__global__ void k_check_offsets(uint32_t n, uint64_t nnz, const uint32_t* off, uint32_t* ctr) {
+__global__ void __launch_bounds__(256) k_check_offsets(uint32_t n, uint64_t nnz, const uint32_t* off, uint32_t* ctr) {
     GRID_LOOP(v, n) {
         if (off[v] > off[v + 1]) atomicOr(&ctr[CTR_INVALID], 1u);
     }
@@ -69,16 +80,13 @@ __global__ void k_check_offsets(uint32_t n, uint64_t nnz, const uint32_t* off, u
 // Rows: ids < n, no self-loop, no repeated entry, symmetric.  The entries
 // of 64 consecutive rows are contiguous in the CSR, so a wave walks them flat,
 // 64 entries per step with one coalesced load: each entry finds its row by
-// the marks its row's start leaves in the wave's 64 words of LDS (an
-// inclusive max-scan), and compares itself with the entry before it (the
-// lane to its left, or the last entry of the previous step).  Every entry
-// (v, w) also looks v up in row w by bisection: when every row turns out to
-// be strictly increasing (CTR_UNSORTED stays 0) that is an exact symmetry
-// test, and a miss sets CTR_MIRROR.  Rows that are not strictly increasing
-// are then checked for repeats one by one (a lane per short row, the whole
-// wave per long row), and symmetry falls back to the signed sum of a hash of
-// each unordered pair, which vanishes when every entry has its mirror (an
-// asymmetric graph passes only on a hash collision).
+// the marks its row's start leaves in 64 words of LDS (an inclusive
+// max-scan), and compares itself with the entry before it (the lane to its
+// left, or the last entry of the previous step).  Rows that are not strictly
+// increasing are then checked for repeats one by one (a lane per short row,
+// the whole wave per long row).  Symmetry: the signed sum of a hash of each
+// unordered pair over all entries vanishes when every entry has its mirror
+// (an asymmetric graph passes only on a hash collision).
 template <typename C>
 __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* off, const C* col,
                                                     uint32_t* ctr, unsigned long long* hsum) {
@@ -96,21 +104,9 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
         return v < w ? h : (0ull - h);
     };
     auto cl = [col](uint32_t e) -> uint32_t { return (uint32_t)col[e]; };
-    // is v in row w (bisection: meaningful when row w is increasing)
-    auto mirrored = [&](uint32_t w, uint32_t v) -> bool {
-        uint32_t lo = off[w], hi = off[w + 1];
-        while (lo < hi) {
-            const uint32_t mid = lo + ((hi - lo) >> 1);
-            const uint32_t x = (uint32_t)col[mid];
-            if (x == v) return true;
-            if (x < v) lo = mid + 1u;
-            else hi = mid;
-        }
-        return false;
-    };
     uint64_t acc = 0;
     uint32_t bad = 0;
-    bool uns = false, miss = false;
+    bool uns = false;
     for (uint32_t base = wave * 64u; base < n; base += waves * 64u) {
         const uint32_t v = base + l;
         const uint32_t last = (n - base < 64u ? n - base : 64u) - 1u;  // last row's lane
@@ -146,7 +142,6 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
                 } else {
                     if (w == rv) bad |= 8u;
                     acc += hash(rv, w);
-                    if (!mirrored(w, rv)) miss = true;
                 }
                 if (e > rs && p >= w) unsorted_here = true;
             }
@@ -178,14 +173,13 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
     }
     if (bad) atomicOr(&ctr[CTR_INVALID], bad);
     if (ballot(uns) != 0ull && l == 0) atomicOr(&ctr[CTR_UNSORTED], 1u);
-    if (ballot(miss) != 0ull && l == 0) atomicOr(&ctr[CTR_MIRROR], 1u);
     acc = wave_sum64(acc);
     if (l == 0 && acc) atomicAdd(hsum, (unsigned long long)acc);
 }
 
 // ------------------------------------------------------------- degrees
 
-__global__ void k_init(uint32_t n, const uint32_t* off, uint32_t* rdeg, uint32_t* gdeg,
+__global__ void __launch_bounds__(256) k_init(uint32_t n, const uint32_t* off, uint32_t* rdeg, uint32_t* gdeg,
                        uint8_t* gin, uint8_t* addf, uint8_t* newly) {
     GRID_LOOP(v, n) {
         uint32_t d = off[v + 1] - off[v];
@@ -203,7 +197,7 @@ __global__ void k_init(uint32_t n, const uint32_t* off, uint32_t* rdeg, uint32_t
 // an independent set, so taking them together is well defined.
 
 template <typename C>
-__global__ void k_greedy_select(uint32_t n, const uint32_t* off, const C* col,
+__global__ void __launch_bounds__(256) k_greedy_select(uint32_t n, const uint32_t* off, const C* col,
                                 const uint32_t* gdeg, uint8_t* sel, uint32_t* ctr_live) {
     // 64 consecutive vertices per wave, one per lane; a row longer than 32
     // entries is walked by the whole wave together (hubs take one pass)
@@ -248,7 +242,7 @@ __global__ void k_greedy_select(uint32_t n, const uint32_t* off, const C* col,
 }
 
 template <typename C>
-__global__ void k_greedy_apply(uint32_t n, const uint32_t* off, const C* col, uint32_t* gdeg,
+__global__ void __launch_bounds__(256) k_greedy_apply(uint32_t n, const uint32_t* off, const C* col, uint32_t* gdeg,
                                uint8_t* sel, uint8_t* gin, const uint32_t* ctr_live,
                                uint32_t* ctr_size) {
     if (*ctr_live == 0) return;
@@ -275,7 +269,7 @@ __global__ void k_greedy_apply(uint32_t n, const uint32_t* off, const C* col, ui
 
 // the greedy restarted on what the root rules left: working degrees of the
 // live vertices only, and the vertices the rules forced already in its cover
-__global__ void k_greedy_rest(uint32_t n, const uint32_t* rdeg, uint32_t* gdeg, uint8_t* gin) {
+__global__ void __launch_bounds__(256) k_greedy_rest(uint32_t n, const uint32_t* rdeg, uint32_t* gdeg, uint8_t* gin) {
     GRID_LOOP(v, n) {
         const uint32_t d = rdeg[v];
         gdeg[v] = rlive(d) ? d : 0u;
@@ -312,7 +306,7 @@ __device__ __forceinline__ bool r_adjacent(const uint32_t* off, const C* col, ui
 }
 
 template <typename C>
-__global__ void k_reduce_decide(uint32_t n, const uint32_t* off, const C* col,
+__global__ void __launch_bounds__(256) k_reduce_decide(uint32_t n, const uint32_t* off, const C* col,
                                 const uint32_t* rdeg, uint8_t* addf, uint32_t* ctr,
                                 uint32_t round, int best0, int sorted) {
     // the previous round fired nothing: the fixpoint is reached (this
@@ -356,7 +350,7 @@ __global__ void k_reduce_decide(uint32_t n, const uint32_t* off, const C* col,
     block_atomic_add(&ctr[CTR_FIRED + (round & 1u)], fired);
 }
 
-__global__ void k_reduce_mark(uint32_t n, uint32_t* rdeg, uint8_t* addf, uint8_t* newly,
+__global__ void __launch_bounds__(256) k_reduce_mark(uint32_t n, uint32_t* rdeg, uint8_t* addf, uint8_t* newly,
                               uint32_t* ctr, uint32_t round) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr[CTR_FIRED + ((round + 1u) & 1u)] = 0;
     if (ctr[CTR_FIRED + (round & 1u)] == 0) return;
@@ -418,6 +412,7 @@ __global__ void __launch_bounds__(256) k_reduce_remove(uint32_t n, const uint32_
 // totals, per-block scan plus its offset.  2048 items per 256-thread block.
 
 constexpr uint32_t SCAN_T = 256, SCAN_PER = 8, SCAN_ITEMS = SCAN_T * SCAN_PER;
+static_assert(sizeof(uint32_t) * (SCAN_T / 64u) <= SIDE_LDS_MAX, "scan partial sums");
 
 template <typename T>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* sh, uint32_t* total) {
@@ -436,7 +431,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* sh, ui
 }
 
 template <typename T>
-__global__ void k_scan_totals(const T* in, uint32_t N, uint32_t* sums) {
+__global__ void __launch_bounds__(256) k_scan_totals(const T* in, uint32_t N, uint32_t* sums) {
     __shared__ uint32_t sh[SCAN_T / 64];
     const uint32_t base = blockIdx.x * SCAN_ITEMS + threadIdx.x * SCAN_PER;
     uint32_t x = 0;
@@ -447,7 +442,7 @@ __global__ void k_scan_totals(const T* in, uint32_t N, uint32_t* sums) {
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-__global__ void k_scan_sums(uint32_t* sums, uint32_t nb) {
+__global__ void __launch_bounds__(256) k_scan_sums(uint32_t* sums, uint32_t nb) {
     __shared__ uint32_t sh[SCAN_T / 64];
     uint32_t carry = 0;
     for (uint32_t base = 0; base < nb; base += SCAN_T) {
@@ -463,7 +458,7 @@ __global__ void k_scan_sums(uint32_t* sums, uint32_t nb) {
 }
 
 template <typename T>
-__global__ void k_scan_apply(const T* in, uint32_t N, const uint32_t* sums, uint32_t* out,
+__global__ void __launch_bounds__(256) k_scan_apply(const T* in, uint32_t N, const uint32_t* sums, uint32_t* out,
                              uint32_t nb) {
     __shared__ uint32_t sh[SCAN_T / 64];
     const uint32_t base = blockIdx.x * SCAN_ITEMS + threadIdx.x * SCAN_PER;
@@ -484,11 +479,11 @@ __global__ void k_scan_apply(const T* in, uint32_t N, const uint32_t* sums, uint
 
 // ------------------------------------------------------------- induce
 
-__global__ void k_live_flags(uint32_t n, const uint32_t* rdeg, uint32_t* flag, int keep_all) {
+__global__ void __launch_bounds__(256) k_live_flags(uint32_t n, const uint32_t* rdeg, uint32_t* flag, int keep_all) {
     GRID_LOOP(v, n) flag[v] = (keep_all || rlive(rdeg[v])) ? 1u : 0u;
 }
 
-__global__ void k_induce_deg(uint32_t n, const uint32_t* rdeg, const uint32_t* newid,
+__global__ void __launch_bounds__(256) k_induce_deg(uint32_t n, const uint32_t* rdeg, const uint32_t* newid,
                              uint32_t* kdeg, uint32_t* oldid, uint32_t* ctr, int keep_all) {
     uint32_t mx = 0;
     GRID_LOOP(v, n) {
@@ -507,7 +502,7 @@ __global__ void k_induce_deg(uint32_t n, const uint32_t* rdeg, const uint32_t* n
 }
 
 template <typename C, typename CO>
-__global__ void k_induce_cols(uint32_t np, const uint32_t* off, const C* col,
+__global__ void __launch_bounds__(256) k_induce_cols(uint32_t np, const uint32_t* off, const C* col,
                               const uint32_t* rdeg, const uint32_t* newid,
                               const uint32_t* oldid, const uint32_t* koff, CO* kcol) {
     // 64 consecutive new vertices per wave, one per lane; a row longer than
@@ -561,19 +556,19 @@ __global__ void k_induce_cols(uint32_t np, const uint32_t* off, const C* col,
 // flags[v] = 1 for the final cover: root-forced vertices plus the kernel
 // cover (mapped back) when the search improved on the greedy bound, else the
 // greedy cover itself.
-__global__ void k_cover_base(uint32_t n, const uint32_t* rdeg, const uint8_t* gin,
+__global__ void __launch_bounds__(256) k_cover_base(uint32_t n, const uint32_t* rdeg, const uint8_t* gin,
                              int improved, uint32_t* flags) {
     GRID_LOOP(v, n) flags[v] = improved ? (rdeg[v] == RIN ? 1u : 0u) : (uint32_t)gin[v];
 }
 
-__global__ void k_cover_kernel(uint32_t np, const uint32_t* oldid, const uint32_t* bitmap,
+__global__ void __launch_bounds__(256) k_cover_kernel(uint32_t np, const uint32_t* oldid, const uint32_t* bitmap,
                                uint32_t* flags) {
     GRID_LOOP(i, np) {
         if ((bitmap[i >> 5] >> (i & 31u)) & 1u) flags[oldid[i]] = 1u;
     }
 }
 
-__global__ void k_cover_list(uint32_t n, const uint32_t* flags, const uint32_t* pos,
+__global__ void __launch_bounds__(256) k_cover_list(uint32_t n, const uint32_t* flags, const uint32_t* pos,
                              uint32_t* out) {
     GRID_LOOP(v, n) {
         if (flags[v]) out[pos[v]] = v;
@@ -618,15 +613,12 @@ hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* 
                            g.off, (const uint32_t*)g.col, ctr, hsum);
     if ((e = hipGetLastError())) return e;
     unsigned long long hs = 0;
-    uint32_t uns = 1, miss = 1;
+    uint32_t uns = 1;
     if ((e = hipMemcpyAsync(&bad, ctr + CTR_INVALID, 4, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipMemcpyAsync(&uns, ctr + CTR_UNSORTED, 4, hipMemcpyDeviceToHost, st))) return e;
-    if ((e = hipMemcpyAsync(&miss, ctr + CTR_MIRROR, 4, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipMemcpyAsync(&hs, hsum, 8, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipStreamSynchronize(st))) return e;
-    // increasing rows: the mirror of every entry was looked up (exact);
-    // otherwise the pair-hash sum must vanish
-    if (uns == 0 ? miss != 0 : hs != 0) bad |= 64u;
+    if (hs != 0) bad |= 64u;
     *bad_host = bad;
     if (sorted_host) *sorted_host = !bad && uns == 0;
     return hipSuccess;
@@ -682,7 +674,10 @@ static hipError_t reduce_t(const RootGraph& g, const RootBufs& b, int best0, hip
                            uint32_t max_rounds, uint32_t* rounds) {
     const C* col = (const C*)g.col;
     hipError_t e;
-    const uint32_t grid = grid_for(g.n);
+    // decide and mark end with one atomic per block on a single counter:
+    // at most 1024 blocks, so a round where most blocks fire does not
+    // serialise thousands of them
+    const uint32_t grid = std::min<uint32_t>(grid_for(g.n), 1024u);
     uint32_t r = 0;
     for (;;) {
         for (uint32_t j = 0; j < 4; ++j, ++r) {

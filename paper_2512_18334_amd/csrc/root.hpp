@@ -20,7 +20,6 @@ enum {
     CTR_CROWN_M = 14,   // crown: vertices matched by the last proposal rounds
     CTR_CROWN_H = 15,   // crown: |H| of the last crown
     CTR_CROWN_I = 16,   // crown: |I| summed over the crowns of a solve
-    CTR_MIRROR = 17,    // validation: an entry whose mirror was not found
     CTR_COUNT = 24
 };
 

@@ -151,8 +151,9 @@ __global__ void batch_init_kernel(SearchArgs a, BatchDesc d) {
         c->inst_next = 0;
         c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
         c->stale = c->local_views = 0;
+        for (int i = 0; i < 8; ++i) c->comp_hist[i] = 0;
         for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
-        c->bytes_nodes = c->bytes_registry = 0;
+        c->bytes_nodes = c->bytes_registry = c->bytes_rows = 0;
     }
 }
 
@@ -229,8 +230,9 @@ __global__ void serve_init_kernel(SearchArgs a, uint64_t host_words) {
         c->closed = 0;
         c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
         c->stale = c->local_views = 0;
+        for (int i = 0; i < 8; ++i) c->comp_hist[i] = 0;
         for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
-        c->bytes_nodes = c->bytes_registry = 0;
+        c->bytes_nodes = c->bytes_registry = c->bytes_rows = 0;
     }
 }
 

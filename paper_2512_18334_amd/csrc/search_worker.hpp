@@ -149,9 +149,11 @@ struct Worker {
     int c_done, c_inst_state, c_idle, c_best, c_best_scope;
     int64_t c_queued;
     uint64_t nodes, cbr, comps, dons, pushes, lviews, nodes_flushed;
+    uint32_t chist[8];  // branches on components by components registered
     uint64_t cyc[6];
     uint64_t t_mark;
     uint64_t b_nodes, b_reg;  // algorithmic bytes written (node slots; registry)
+    uint64_t b_rows;          // CSR bytes of removed vertices' rows read from HBM views
     uint32_t inst;            // instance of the current node (batches)
     uint64_t inst_cnt;        // its nodes not yet added to inst_nodes
 
@@ -172,7 +174,7 @@ struct Worker {
         G = reinterpret_cast<uint32_t*>(lds + a.lds_G);
         stack = a.stacks + (size_t)blockIdx.x * a.stack_depth * a.slot_bytes;
         bot = top = 0;
-        b_nodes = b_reg = 0;
+        b_nodes = b_reg = b_rows = 0;
         inst = 0;
         inst_cnt = 0;
         for (int i = 0; i < 6; ++i) cyc[i] = 0;
@@ -183,6 +185,7 @@ struct Worker {
         c_best_scope = -1;
         c_queued = 0;
         nodes = cbr = comps = dons = pushes = lviews = nodes_flushed = 0;
+        for (int i = 0; i < 8; ++i) chist[i] = 0;
         known_connected = false;
         induce_first = false;
         view = -1;
@@ -370,6 +373,12 @@ struct Worker {
             nn += popc(m);
         }
         wsync();
+        if (!vlds) {
+            // the rows (and their offsets) come from a view in HBM
+            uint32_t rl = 0;
+            for (uint32_t i = l; i < nn; i += 64) rl += vo(list[i] + 1) - vo(list[i]);
+            b_rows += 4ull * wave_sum(rl) + 8ull * nn;
+        }
         for_rows([&](uint32_t x) { return vo(x); }, [&](uint32_t e) { return vc(e); }, list, nn, MK,
                  [&](bool ok, uint32_t, uint32_t w) {
             if (ok && DG::live(DG::get(deg, w))) DG::dec(deg, w);
@@ -687,7 +696,7 @@ struct Worker {
 
     // The node holds exactly its scope's component, in the ids of the view
     // it was found in.  Induce the component as a subgraph of its own (local
-    // ids = positions in the live list), make it the entry's view, rewrite
+    // ids = positions in a breadth-first order), make it the entry's view, rewrite
     // the entry's initial cover in local ids (under its lock: a parent may be
     // reading the children's covers), and move the degree array to local ids.
     __device__ __forceinline__ void adopt_component_view() {
@@ -697,8 +706,9 @@ struct Worker {
         for (uint32_t i = l; i < size; i += 64) dsum += DG::get(deg, L[i]);
         const uint32_t nnz = wave_sum(dsum);
         if (size < 2u || size + 1u + nnz > A.gcache_words || size >= vn) return;
-        for (uint32_t i = l; i < size; i += 64) Q[i] = L[i];
-        wsync();
+        // local ids in breadth-first order from the component's lowest id,
+        // the order a child induced at registration gets (Q)
+        if (find_components() != 1u) return;
         const int e = scope;
         lock(e);
         const uint32_t g_at = induce_component(0, size, nnz, R + A.n_pad + 64u, L);
@@ -1459,6 +1469,12 @@ struct Worker {
         // entries, covers and graphs are complete before any child can run
         if (l == 0) publish_order();
         cbr += 1;
+        {
+            // Table III: components per branch, in power-of-two buckets
+            uint32_t bk = 0;
+            while (bk < 7u && (2u << bk) < nt) ++bk;
+            ++chist[bk];
+        }
         comps += nt;
         // children 1..nt-1 go out as nodes holding only their component,
         // built in L (free until child 0 rebuilds it)
@@ -2126,6 +2142,9 @@ struct Worker {
             for (int i = 0; i < 6; ++i) add_relaxed(&A.ctl->cyc[i], cyc[i]);
             add_relaxed(&A.ctl->bytes_nodes, b_nodes);
             add_relaxed(&A.ctl->bytes_registry, b_reg);
+            add_relaxed(&A.ctl->bytes_rows, b_rows);
+            for (int i = 0; i < 8; ++i)
+                if (chist[i]) add_relaxed(&A.ctl->comp_hist[i], chist[i]);
         }
     }
 
@@ -2339,8 +2358,9 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         c->inst_next = 0;
         c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
         c->stale = c->local_views = 0;
+        for (int i = 0; i < 8; ++i) c->comp_hist[i] = 0;
         for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
-        c->bytes_nodes = c->bytes_registry = 0;
+        c->bytes_nodes = c->bytes_registry = c->bytes_rows = 0;
         RegEntry r = {};
         r.best = best0;
         r.live = 1;

@@ -136,6 +136,82 @@ struct Server {
     vc_status start(Req& r);
     vc_status finish(Req& r, int state);
     vc_status check_done();
+    double last_dump = 0;
+    // An admitted instance whose FIN never comes although no node of the
+    // launch exists any more (no busy worker, nothing queued, nothing left
+    // to claim, the node count still) would keep the server from closing
+    // the launch and from shutting down: after 200 ms of that state it is
+    // answered with VC_EDEVICE and its slot is freed.  (An internal error:
+    // its LiveNodes count did not return to 0.)
+    double still_since = 0, last_still_check = 0;
+    uint64_t still_nodes = ~0ull;
+    vc_status check_stuck() {
+        const double t = now_ms();
+        if (t - last_still_check < 20.0) return VC_OK;
+        last_still_check = t;
+        Ctl h{};
+        HIPCHK(hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ss));
+        HIPCHK(hipStreamSynchronize(ss));
+        const bool quiet = h.outstanding == 0 && h.wl_head == h.wl_tail &&
+                           h.inst_next >= h.inst_avail && h.nodes == still_nodes;
+        still_nodes = h.nodes;
+        if (!quiet) {
+            still_since = 0;
+            return VC_OK;
+        }
+        if (still_since == 0) still_since = t;
+        if (t - still_since < 200.0) return VC_OK;
+        still_since = 0;
+        debug_dump_now(h);
+        for (uint32_t i = 0; i < published; ++i) {
+            auto& p = slot_req[i];
+            if (!p || p->done || (h_state[i] & INST_FIN)) continue;
+            fprintf(stderr, "libvc serve: request %llu (slot %u) has no node left but did not "
+                            "finish; answered with VC_EDEVICE\n",
+                    (unsigned long long)p->ticket, i);
+            p->res.status = VC_EDEVICE;
+            --active;
+            auto keep = p;
+            p = nullptr;
+            complete(*keep);
+        }
+        return VC_OK;
+    }
+    // VC_DEBUG_SERVE: every 5 s while instances are active, the state of
+    // the resident launch and of every unanswered instance (stderr)
+    void debug_dump() {
+        const double t = now_ms();
+        if (t - last_dump < 5000.0) return;
+        last_dump = t;
+        Ctl h{};
+        if (hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ss) != hipSuccess ||
+            hipStreamSynchronize(ss) != hipSuccess)
+            return;
+        debug_dump_now(h);
+    }
+    void debug_dump_now(const Ctl& h) {
+        const double t = now_ms();
+        fprintf(stderr,
+                "libvc serve: published %u active %u outstanding %d idle %d head %llu tail %llu "
+                "next %u avail %u closed %d done %d err %d nodes %llu\n",
+                published, active, h.outstanding, h.idle, (unsigned long long)h.wl_head,
+                (unsigned long long)h.wl_tail, h.inst_next, h.inst_avail, h.closed, h.done, h.err,
+                (unsigned long long)h.nodes);
+        for (uint32_t i = 0; i < published; ++i) {
+            auto& p = slot_req[i];
+            if (!p || p->done) continue;
+            RegEntry e{};
+            if (hipMemcpyAsync(&e, a.reg + i, sizeof(e), hipMemcpyDeviceToHost, ss) != hipSuccess ||
+                hipStreamSynchronize(ss) != hipSuccess)
+                return;
+            fprintf(stderr,
+                    "libvc serve:   slot %u ticket %llu kind %d n %u np %u state %d nodes %llu "
+                    "live %d best %d cover %d waited %.0f ms\n",
+                    i, (unsigned long long)p->ticket, p->kind, p->n, p->np, h_state[i],
+                    (unsigned long long)h_nodes[i], e.live, e.best, e.cover_size,
+                    t - p->t_submit);
+        }
+    }
     void fail_active(vc_status e);
     void complete(Req& r);
     void loop();
@@ -634,6 +710,11 @@ vc_status Server::check_done() {
             complete(*p);  // a PVC yes: answered while its nodes drain
         }
     }
+    if (getenv("VC_DEBUG_SERVE")) debug_dump();
+    {
+        vc_status ss_ = check_stuck();
+        if (ss_) return ss_;
+    }
     // a FIN that arrived for an already answered PVC instance frees its slot
     for (uint32_t i = 0; i < published; ++i) {
         auto& p = slot_req[i];
@@ -668,11 +749,21 @@ void Server::loop() {
                 queue.push_back(incoming.front());
                 incoming.pop_front();
             }
+            if (stop)
+                for (auto& q : queue) q->canceled = true;  // not started: dropped
             if (stop && queue.empty() && active == 0) break;
         }
         bool progress = false;
         if (resident && active) {
             if (check_done()) fail_active(VC_EDEVICE);
+        }
+        if (!resident && active) {
+            // the launch ended with admitted instances unfinished (an
+            // internal error): answer them rather than wait for ever
+            fprintf(stderr, "libvc serve: %u admitted requests unfinished after their launch "
+                            "ended; answered with VC_EDEVICE\n", active);
+            fail_active(VC_EDEVICE);
+            progress = true;
         }
         if (!queue.empty()) {
             auto r = queue.front();

@@ -34,6 +34,7 @@ VC_OPT_CHECK_REGISTRY = 1024
 VC_MIN, VC_PARAM = 0, 1
 
 CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]
+COMP_HIST_BUCKETS = ["2", "3-4", "5-8", "9-16", "17-32", "33-64", "65-128", ">128"]
 
 EXPORTS = ["vc_ctx_create", "vc_ctx_destroy", "vc_validate", "vc_min",
            "vc_param", "vc_min_batch", "vc_param_batch", "vc_submit", "vc_poll",
@@ -93,7 +94,8 @@ class vc_stats(ctypes.Structure):
                 ("stale_reads", ctypes.c_uint64), ("reg_entries", ctypes.c_uint32),
                 ("reg_checked", ctypes.c_uint32), ("reg_open", ctypes.c_uint32),
                 ("reg_parents", ctypes.c_uint32), ("reg_depth", ctypes.c_uint32),
-                ("lists_in_hbm", ctypes.c_uint32)]
+                ("lists_in_hbm", ctypes.c_uint32), ("bytes_rows", ctypes.c_uint64),
+                ("comp_hist", ctypes.c_uint32 * 8)]
 
 
 class VCError(RuntimeError):
@@ -343,6 +345,7 @@ class Solver:
         _check(load().vc_last_stats(self._h, ctypes.byref(s)), "vc_last_stats")
         out = {f: getattr(s, f) for f, _ in vc_stats._fields_}
         out["cycles"] = dict(zip(CYCLE_NAMES, list(s.cycles)))
+        out["comp_hist"] = dict(zip(COMP_HIST_BUCKETS, list(s.comp_hist)))
         return out
 
     def mvc(self, g, want_cover: bool = True) -> Result:

@@ -162,3 +162,16 @@ def test_batch_config4_sample(solver, orc):
         assert int(size) == o["size"], g.name
         checked += 1
     assert checked >= 10
+
+
+def test_autotune_grid_keeps_exact_sizes(libvc):
+    """The batch autotuner on a 2 x 2 grid (waves per CU x worklist depth):
+    every configuration must give the same exact sizes (tune_batch raises
+    otherwise), and the choice is one of the configurations swept."""
+    from paper_2512_18334_amd import autotune
+    graphs = [gg.config4_instance(i) for i in range(96)]
+    grid = {"waves_per_cu": (1, 2), "worklist_cap": (1024, 4096), "donate_min": (48,)}
+    out = autotune.tune_batch(graphs, node_limit=50_000, grid=grid, log=lambda m: None)
+    assert len(out["table"]) == 4
+    assert out["opts"] in [o for o, _ in out["table"]]
+    assert out["ms"] == min(ms for _, ms in out["table"])

@@ -70,8 +70,12 @@ def test_nested_component_branches_complete_once(libvc, orc, level, workers, str
             st = r.stats
             assert st["reg_checked"] == 1
             assert st["reg_open"] == 0, st
-            assert st["reg_depth"] >= level + 1, st
-            assert st["reg_parents"] >= level + 1
+            # the root's branch, the branch after the outer hub and, from
+            # level 2 on, the one after the next hub are forced before any
+            # cover of the scope is known; deeper ones depend on the bounds
+            # found so far and on tie-breaks
+            assert st["reg_depth"] >= min(level + 1, 3), st
+            assert st["reg_parents"] >= min(level + 1, 3)
             assert st["stale_reads"] == 0
 
 

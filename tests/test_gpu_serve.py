@@ -57,7 +57,10 @@ def wait_idle_then(fn, timeout_s=30.0):
 def test_served_mix_matches_oracle_and_alone(solver, orc):
     reqs = request_mix()
     tickets = [solver.submit(g, kind, k) for g, kind, k in reqs]
-    results = [solver.wait(t, g.n) for t, (g, _, _) in zip(tickets, reqs)]
+    results = []
+    for t, (g, _, _) in zip(tickets, reqs):
+        print(f"serve: waiting for {g.name} (ticket {t})", flush=True)
+        results.append(solver.wait(t, g.n))
     for (g, kind, k), (res, cov) in zip(reqs, results):
         assert res["status"] == vc.VC_OK, (g.name, res)
         mvc = orc.mvc(g)["size"]
