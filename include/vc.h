@@ -233,6 +233,8 @@ typedef struct vc_ctx vc_ctx;
  *                call.  VC_EINVAL if only one of the two is given or the
  *                pointer is not device memory of `device`.
  *   opts         may be NULL (defaults).
+ * Creating the first context on a device also looks up the device address
+ * of the library's static scratch used by vc_min_static (no allocation).
  */
 vc_status vc_ctx_create(int device, void *stream, void *arena, uint64_t arena_bytes,
                         const vc_opts *opts, vc_ctx **out);
@@ -259,6 +261,23 @@ vc_status vc_validate(vc_ctx *ctx, const vc_csr *g);
  */
 vc_status vc_min(vc_ctx *ctx, const vc_csr *g, uint32_t *size,
                  uint32_t *cover, uint32_t *cover_len);
+
+/*
+ * vc_min without device memory allocation, for callers that cannot
+ * allocate (code between graph captures, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as vc_min;
+ * every device buffer of the solve is carved from a static 256 MiB scratch
+ * array in the library's device code (one per GPU, held until the process
+ * ends), and the search plan is fitted to it (fewer workers than vc_min
+ * where their stacks would not fit).  Limits: n <= 2^20 and nnz <= 2^24;
+ * a larger graph, or one whose buffers or search do not fit the scratch,
+ * returns VC_ERANGE.  Calls on one GPU share its scratch: calls that
+ * overlap in time (two host threads, or two contexts on one device) race
+ * and must not be made.  Everything the solve needs zeroed is cleared by
+ * the call itself.  VC_EAGAIN while served requests are in flight.
+ */
+vc_status vc_min_static(vc_ctx *ctx, const vc_csr *g, uint32_t *size,
+                        uint32_t *cover, uint32_t *cover_len);
 
 /*
  * Parameterized vertex cover (Sec. II-B, III-E): *yes = 1 iff MVC(G) <= k.

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -682,6 +683,46 @@ vc_status order_after_default(vc_ctx* c) {
 
 }  // namespace vc
 
+namespace {
+
+// Scratch of vc_min_static: a file-scope device array, one copy per GPU.
+// Host code never uses the array's name as an address: its device address
+// on each GPU comes from hipGetSymbolAddress, taken once per device when
+// the first context on that device is created.
+constexpr size_t SCRATCH_BYTES = 256ull << 20;
+constexpr uint32_t STATIC_MAX_N = 1u << 20;
+constexpr uint64_t STATIC_MAX_NNZ = 1ull << 24;
+__device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[MAX_DEVICES] = {};
+hipError_t scratch_err[MAX_DEVICES] = {};
+
+// with `device` current
+void scratch_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (scratch_ptr[device] || scratch_err[device]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        if (getenv("VC_DEBUG"))
+            fprintf(stderr, "libvc: hipGetSymbolAddress(scratch) -> %s\n", hipGetErrorString(e));
+        return;
+    }
+    scratch_ptr[device] = p;
+}
+
+void* scratch_address(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    return scratch_ptr[device];
+}
+
+}  // namespace
+
 extern "C" {
 
 vc_status vc_ctx_create(int device, void* stream, void* arena, uint64_t arena_bytes,
@@ -756,6 +797,9 @@ vc_status vc_ctx_create(int device, void* stream, void* arena, uint64_t arena_by
             return VC_EDEVICE;
         }
     }
+    // the static scratch's address on this device (library set-up, once per
+    // device; vc_min_static reports a failure here)
+    scratch_init(device);
     *out = c;
     return VC_OK;
 }
@@ -763,6 +807,10 @@ vc_status vc_ctx_create(int device, void* stream, void* arena, uint64_t arena_by
 vc_status vc_ctx_destroy(vc_ctx* c) {
     if (!c) return VC_OK;
     hipSetDevice(c->device);
+    if (c->scratch_ctx) {
+        vc_ctx_destroy(c->scratch_ctx);
+        c->scratch_ctx = nullptr;
+    }
     server_shutdown(c);
     if (c->stream) hipStreamSynchronize(c->stream);
     if (c->batch_exec) hipGraphExecDestroy(c->batch_exec);
@@ -807,6 +855,44 @@ vc_status vc_param(vc_ctx* c, const vc_csr* g, uint32_t k, int* yes, uint32_t* c
     if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
     pool_reset(c);
     return solve_one(c, g, 1, k, nullptr, yes, cover, cover_len);
+}
+
+vc_status vc_min_static(vc_ctx* c, const vc_csr* g, uint32_t* size, uint32_t* cover,
+                        uint32_t* cover_len) {
+    if (!c || !size) return VC_EINVAL;
+    vc_status st = check_args(g);
+    if (st) return st;
+    if (g->n > STATIC_MAX_N || g->nnz > STATIC_MAX_NNZ) return VC_ERANGE;
+    if (server_busy(c)) return VC_EAGAIN;
+    if (hipSetDevice(c->device) != hipSuccess) return VC_EDEVICE;
+    void* base = scratch_address(c->device);
+    if (!base) return VC_EDEVICE;
+    if (!c->scratch_ctx) {
+        // host-side state only: the stream, events and device facts are the
+        // caller context's, every device buffer is carved from the scratch
+        vc_ctx* s = new (std::nothrow) vc_ctx();
+        if (!s) return VC_ENOMEM;
+        s->device = c->device;
+        s->stream = c->stream;
+        s->own_stream = false;
+        s->wait_default = c->wait_default;
+        s->cus = c->cus;
+        s->lds_max = c->lds_max;
+        s->wall_khz = c->wall_khz;
+        for (int i = 0; i < 6; ++i) s->ev[i] = c->ev[i];
+        s->shared_events = true;
+        c->scratch_ctx = s;
+    }
+    vc_ctx* s = c->scratch_ctx;
+    s->opts = c->opts;
+    s->pool.base = (uint8_t*)base;
+    s->pool.cap = SCRATCH_BYTES;
+    s->pool.used = 0;
+    pool_reset(s);
+    st = solve_one(s, g, 0, 0, size, nullptr, cover, cover_len);
+    c->last = s->last;
+    // the scratch could not hold the graph's buffers or its search plan
+    return st == VC_ENOMEM ? VC_ERANGE : st;
 }
 
 vc_status vc_last_stats(vc_ctx* c, vc_stats* out) {

@@ -22,7 +22,8 @@ struct DevBuf {
 };
 
 // A fixed region of device memory that a context's buffers are carved from
-// instead of hipMalloc: a caller's arena (vc_ctx_create).  Carving is a bump of `used`; a buffer
+// instead of hipMalloc: a caller's arena (vc_ctx_create) or the library's
+// static scratch (vc_min_static).  Carving is a bump of `used`; a buffer
 // that has to grow takes a new region and leaves its old one unused until
 // the pool is reset, which the blocking entry points do before they start
 // (every buffer of the context is then forgotten).
@@ -139,6 +140,9 @@ struct vc_ctx {
     vc::DevBuf en[13];
     // a caller's arena (vc_ctx_create), else buffers come from hipMalloc
     vc::Pool pool;
+    // the context that vc_min_static runs on: same device, stream, events
+    // and options, with its pool over the library's static scratch
+    vc_ctx* scratch_ctx = nullptr;
     bool shared_events = false;  // events belong to another context
     bool wait_default = false;   // own stream: device inputs wait for the default stream
 };

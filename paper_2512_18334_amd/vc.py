@@ -38,7 +38,8 @@ COMP_HIST_BUCKETS = ["2", "3-4", "5-8", "9-16", "17-32", "33-64", "65-128", ">12
 
 EXPORTS = ["vc_ctx_create", "vc_ctx_destroy", "vc_validate", "vc_min",
            "vc_param", "vc_min_batch", "vc_param_batch", "vc_submit", "vc_poll",
-           "vc_cancel", "vc_last_stats", "vc_status_str", "vc_param_enum"]
+           "vc_cancel", "vc_last_stats", "vc_status_str", "vc_param_enum",
+           "vc_min_static"]
 
 
 class vc_csr(ctypes.Structure):
@@ -133,6 +134,8 @@ def load():
     lib.vc_validate.argtypes = [p, ctypes.POINTER(vc_csr)]
     lib.vc_min.restype = ctypes.c_int
     lib.vc_min.argtypes = [p, ctypes.POINTER(vc_csr), u32p, u32p, u32p]
+    lib.vc_min_static.restype = ctypes.c_int
+    lib.vc_min_static.argtypes = [p, ctypes.POINTER(vc_csr), u32p, u32p, u32p]
     lib.vc_param.restype = ctypes.c_int
     lib.vc_param.argtypes = [p, ctypes.POINTER(vc_csr), ctypes.c_uint32,
                              ctypes.POINTER(ctypes.c_int), u32p, u32p]
@@ -358,6 +361,20 @@ class Solver:
         st = load().vc_min(self._h, ctypes.byref(c), ctypes.byref(size), cp,
                            ctypes.byref(clen))
         _check(st, "vc_min")
+        return Result(int(size.value), None, cov[:clen.value].copy(), self.stats())
+
+    def mvc_static(self, g, want_cover: bool = True) -> Result:
+        """vc_min_static: vc_min on the library's static scratch (no device
+        memory is allocated by the call)."""
+        c, keep = self._csr(g)
+        n = int(c.n)
+        size = ctypes.c_uint32(0)
+        clen = ctypes.c_uint32(0)
+        cov = np.zeros(max(n, 1), np.uint32)
+        cp = cov.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if want_cover else None
+        st = load().vc_min_static(self._h, ctypes.byref(c), ctypes.byref(size), cp,
+                                  ctypes.byref(clen))
+        _check(st, "vc_min_static")
         return Result(int(size.value), None, cov[:clen.value].copy(), self.stats())
 
     def pvc(self, g, k: int, want_cover: bool = True) -> Result:
