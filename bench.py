@@ -184,7 +184,8 @@ def bench_blocks_hubs(args, torch, gg, vc):
     g = gg.config2_blocks_hubs()
     dg = vc.DeviceGraph.from_graph(g, "cuda:0")
     torch.cuda.synchronize()
-    solver = vc.Solver(0)
+    solver = vc.Solver(0, flags=args.flags, workers=args.workers, donate_min=args.donate_min,
+                       donate_slack=args.donate_slack, small_max=args.small_max)
     for _ in range(args.warmup):
         solver.mvc(dg)
     torch.cuda.synchronize()
@@ -612,7 +613,7 @@ def bench_serve(args, torch, gg, vc):
 
 ABLATIONS = [("proposed", 0), ("no_components", 1), ("no_reduce_induce", 32),
              ("no_compaction", 64), ("no_load_balance", 2), ("no_small_solver", 16),
-             ("crown_forced", 128)]
+             ("crown_forced", 128), ("eager_induce", 2048)]
 
 
 def bench_ablation(args, torch, gg, vc):
@@ -793,6 +794,12 @@ def main():
                     default="blocks_hubs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="vc_opts.flags for the default workload (ablation switches)")
+    ap.add_argument("--workers", type=int, default=0, help="vc_opts.workers (0: default)")
+    ap.add_argument("--donate-min", type=int, default=0, help="vc_opts.donate_min (0: default)")
+    ap.add_argument("--donate-slack", type=int, default=0, help="vc_opts.donate_slack")
+    ap.add_argument("--small-max", type=int, default=0, help="vc_opts.small_max (0: default)")
     ap.add_argument("--no-legs", action="store_true",
                     help="default workload only: skip the batch and served legs")
     ap.add_argument("--copy-mib", type=int, default=0,

@@ -94,12 +94,29 @@ typedef struct {
                                    coherent accesses and completion waits
                                    the search always uses (all entry
                                    points)                                  */
+#define VC_OPT_EAGER_INDUCE 2048u /* the worker that branches on components
+                                   induces every component's subgraph at
+                                   registration (by default only the one it
+                                   continues with; each other component's
+                                   subgraph is induced by the worker that
+                                   starts it)                               */
+#define VC_OPT_NO_ROOT_CACHE 4096u /* single solves: read the root's induced
+                                   subgraph from HBM at every node instead
+                                   of copying it into a worker's LDS graph
+                                   cache when it fits                      */
 #define VC_OPT_CHECK_REGISTRY 1024u /* after a search that ran to its end,
                                    read the component branch registry back
                                    and check its end state (Sec. III-C):
                                    every LiveNodes and LiveComps counter at
                                    0 and every entry completed exactly once;
                                    the result is in vc_stats (single solves) */
+#define VC_OPT_POISON 8192u     /* testing: fill every device buffer the
+                                   context allocates or carves with the byte
+                                   0xA7 first (every low flag bit set, every
+                                   index out of range), so that a read of
+                                   memory no step of the call wrote shows up
+                                   (slower; synchronises the device at each
+                                   allocation)                              */
 
 /*
  * Tuning knobs.  Zero in any field selects the library default.
@@ -135,8 +152,10 @@ typedef struct {
  *                 instances keep the workers busy).  VC_OPT_NO_SMALL turns
  *                 it off.
  *   gcache_words  LDS graph cache per worker, in 32-bit words: components
- *                 whose induced subgraph fits are re-induced with local ids
- *                 (default: the most that still fits three workers per CU).
+ *                 whose induced subgraph fits are re-induced with local ids,
+ *                 and the root's induced subgraph is held there when it fits
+ *                 (default: what the LDS share of the workers per CU leaves,
+ *                 at most 32K words).
  */
 typedef struct {
     uint32_t workers;

@@ -50,10 +50,33 @@ def _compile(entry) -> str:
     src, name, extra = entry
     obj = os.path.join(BUILD_DIR, name + ".o")
     cmd = [_hipcc(), *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    if name.startswith("search_d"):
+        # the search kernel's register use: a spill to scratch (the worker
+        # object no longer kept in registers) costs far more than it looks
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    if name.startswith("search_d"):
+        _check_resources(name, r.stderr)
     return obj
+
+
+SCRATCH_WARN = 64  # bytes per lane
+
+
+def _check_resources(name: str, remarks: str) -> None:
+    kernel, lines = None, []
+    for line in remarks.splitlines():
+        if "Function Name:" in line:
+            kernel = line.split("Function Name:")[1].split()[0]
+        elif kernel and "search_kernel" in kernel and "ScratchSize" in line:
+            size = int(line.split("]:")[1].split()[0])
+            lines.append(f"{name} {kernel} scratch {size} B/lane")
+            if size > SCRATCH_WARN:
+                print(f"warning: {kernel} ({name}) spills {size} bytes per lane to scratch")
+    with open(os.path.join(BUILD_DIR, name + ".resources.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def build(verbose: bool = False) -> str:

@@ -77,7 +77,7 @@ vc_status plan_workers(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* l
         for (uint32_t per = (workers + cus - 1u) / cus; per >= 1; --per) {
             const uint32_t share = cu_lds / per;
             if (share > base_lds + 4096u) {
-                gwords = std::min<uint32_t>(16384u, (share - base_lds - 64u) / 4u);
+                gwords = std::min<uint32_t>(32768u, (share - base_lds - 64u) / 4u);
                 break;
             }
         }
@@ -346,7 +346,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         uint32_t cnt = 0;
         HIPCHK(hipMemcpyAsync(&cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (cnt != gsize) return VC_EDEVICE;
+        if (cnt != gsize) return broken("greedy cover size");
         out->size = gsize;
         out->yes = yes;
         out->cover_count = cnt;
@@ -499,6 +499,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
 
         SearchArgs a{};
         a.n = np;
+        a.nnz = (uint32_t)nnzp;
         a.n_pad = n_pad;
         a.off = b.koff;
         a.col = (const uint32_t*)b.kcol;
@@ -571,6 +572,9 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         HIPCHK(hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
         stv.ms_induce = ms;
         if (ctl.err) {
+            if (getenv("VC_DEBUG"))
+                fprintf(stderr, "libvc: search stopped: status %d at check %d\n", ctl.err,
+                        ctl.err_site);
             c->last = stv;
             return (vc_status)ctl.err;
         }
@@ -593,7 +597,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         }
         if (root.best < kbest0) {
             // internal invariant: the root's bitmap holds a cover of size Best
-            if (root.cover_size != root.best) return VC_EDEVICE;
+            if (root.cover_size != root.best) {
+                c->last = stv;
+                return broken("root cover size != Best");
+            }
             improved = true;
             kbest = root.best;
             root_bitmap = (uint32_t*)c->bitmaps.p;
@@ -613,7 +620,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     HIPCHK(hipStreamSynchronize(s));
     // internal invariant: |cover| == size (MVC); in PVC a cover assembled
     // while components were still improving may be smaller than its bound
-    if (pvc ? cnt > size : cnt != size) return VC_EDEVICE;
+    if (pvc ? cnt > size : cnt != size) {
+        c->last = stv;
+        return broken("assembled cover size");
+    }
     out->size = pvc ? cnt : size;
     out->yes = pvc ? (size <= k) : 1;
     out->cover_count = cnt;
@@ -755,6 +765,7 @@ vc_status vc_ctx_create(int device, void* stream, void* arena, uint64_t arena_by
     if (!c) return VC_ENOMEM;
     c->device = device;
     if (opts) c->opts = *opts;
+    c->pool.poison = (c->opts.flags & VC_OPT_POISON) != 0;
     if (arena) {
         const uintptr_t a0 = (uintptr_t)arena, a1 = (a0 + 255u) & ~(uintptr_t)255u;
         c->pool.base = (uint8_t*)a1;
@@ -888,6 +899,7 @@ vc_status vc_min_static(vc_ctx* c, const vc_csr* g, uint32_t* size, uint32_t* co
     s->pool.base = (uint8_t*)base;
     s->pool.cap = SCRATCH_BYTES;
     s->pool.used = 0;
+    s->pool.poison = c->pool.poison;
     pool_reset(s);
     st = solve_one(s, g, 0, 0, size, nullptr, cover, cover_len);
     c->last = s->last;

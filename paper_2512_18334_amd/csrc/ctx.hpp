@@ -31,7 +31,14 @@ struct Pool {
     uint8_t* base = nullptr;  // null: buffers come from hipMalloc
     size_t cap = 0;
     size_t used = 0;
+    bool poison = false;  // VC_OPT_POISON: fill new buffers with 0xA7
 };
+
+inline hipError_t poison_fill(const Pool& pool, void* p, size_t bytes) {
+    if (!pool.poison) return hipSuccess;
+    hipError_t e = hipMemset(p, 0xA7, bytes);
+    return e ? e : hipDeviceSynchronize();
+}
 
 // grow b to at least `bytes` (contents are not kept)
 inline hipError_t ensure(Pool& pool, DevBuf& b, size_t bytes) {
@@ -45,7 +52,7 @@ inline hipError_t ensure(Pool& pool, DevBuf& b, size_t bytes) {
         b.cap = want;
         b.pooled = true;
         pool.used = at + want;
-        return hipSuccess;
+        return poison_fill(pool, b.p, want);
     }
     if (b.p) {
         hipError_t e = b.pooled ? hipSuccess : hipFree(b.p);
@@ -57,7 +64,7 @@ inline hipError_t ensure(Pool& pool, DevBuf& b, size_t bytes) {
     if (e) return e;
     b.cap = want;
     b.pooled = false;
-    return hipSuccess;
+    return poison_fill(pool, b.p, want);
 }
 
 // drop a buffer without freeing it (pooled buffers only)
@@ -96,6 +103,15 @@ inline vc_status hip_status(hipError_t e) {
     return VC_EDEVICE;
 }
 
+}  // namespace vc
+
+namespace vc {
+// A host-side consistency check of a search's result failed: VC_EDEVICE,
+// named on stderr under VC_DEBUG.
+inline vc_status broken(const char* what) {
+    if (getenv("VC_DEBUG")) fprintf(stderr, "libvc: internal check failed: %s\n", what);
+    return VC_EDEVICE;
+}
 }  // namespace vc
 
 #define HIPCHK(x)                                                                 \

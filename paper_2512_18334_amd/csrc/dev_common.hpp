@@ -156,6 +156,9 @@ __device__ __forceinline__ void fence_acquire() {
 __device__ __forceinline__ void fence_release() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
+__device__ __forceinline__ void fence_seq() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+}
 __device__ __forceinline__ bool cas_acquire(int* p, int expect, int desired) {
     return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_ACQUIRE,
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -23,7 +23,7 @@ struct SlotHdr {
     uint32_t stamp;    // worklist position the slot was published for (0 on stacks)
     int32_t view;      // registry entry whose graph the degree array indexes
     uint32_t inst;     // instance the node belongs to (batches; 0 otherwise)
-    uint32_t pad;
+    uint32_t flags;    // SLOT_COUNTED, SLOT_INDUCE
 };
 static_assert(sizeof(SlotHdr) == 32, "slot header is 32 bytes");
 
@@ -72,14 +72,16 @@ struct Ctl {
     int done;         // stop flag (PVC answer found, error, limit)
     int err;          // vc_status of a device-side failure
     uint32_t reg_next;
-    int _p4[29];
+    int err_site;     // which check raised it (FAIL_*), for diagnostics
+    int _p4[28];
     uint64_t arena_next;  // words of the graph arena in use
     uint64_t _p6[15];
     uint32_t inst_next;   // batches: next instance to claim
     uint32_t _p8[31];
     uint32_t inst_avail;  // serving: instances published so far (host writes)
     int closed;           // serving: no more instances will be published
-    uint32_t _p9[30];
+    uint32_t quit_epoch;  // serving: the launch of this epoch is ending (no new claims)
+    uint32_t _p9[29];
     uint64_t nodes;   // statistics
     uint64_t comp_branches;
     uint64_t components;
@@ -99,6 +101,8 @@ struct Ctl {
     uint64_t bytes_rows;      // CSR bytes read from HBM for the rows of removed vertices
     uint64_t _p7[7];
 };
+// Device-side checks that stop a search (Ctl::err_site)
+enum { FAIL_NONE = 0, FAIL_STALE_SLOT, FAIL_ARENA, FAIL_NODE_LIMIT, FAIL_SMALL_STACK, FAIL_WATCHDOG };
 enum { CYC_FETCH = 0, CYC_REDUCE, CYC_COMPONENTS, CYC_BRANCH, CYC_COMPLETE, CYC_IDLE };
 
 // Per-instance state bits of a batch (SearchArgs::inst_state)
@@ -110,6 +114,7 @@ enum : int {
 
 struct SearchArgs {
     uint32_t n;           // vertices of the induced subgraph (root view)
+    uint32_t nnz;         // its CSR entries
     uint32_t n_pad;       // largest degree array (multiple of 64)
     const uint32_t* off;  // CSR of the induced subgraph
     const uint32_t* col;
@@ -152,6 +157,8 @@ struct SearchArgs {
     // instance i like a PVC answer does.
     uint32_t serve;
     const int* inst_cancel;
+    uint64_t linger_ticks;  // serving: an empty launch ends after this long
+    uint32_t launch_epoch;  // serving: number of this launch of the resident search
     uint32_t small_max;  // live vertices up to which a node is solved in registers (0: never)
     // Lists in HBM (nodes whose lists do not fit LDS): the live list and the
     // scratch lists L, Q, R of worker w are at hl_base + w * hl_stride (the

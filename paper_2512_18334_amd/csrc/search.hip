@@ -146,6 +146,7 @@ __global__ void batch_init_kernel(SearchArgs a, BatchDesc d) {
         c->idle = 0;
         c->done = 0;
         c->err = 0;
+        c->err_site = 0;
         c->reg_next = (d.count + 1u) & ~1u;
         c->arena_next = d.inst_words;
         c->inst_next = 0;
@@ -223,11 +224,13 @@ __global__ void serve_init_kernel(SearchArgs a, uint64_t host_words) {
         c->idle = 0;
         c->done = 0;
         c->err = 0;
+        c->err_site = 0;
         c->reg_next = (a.n_roots + 1u) & ~1u;
         c->arena_next = host_words;
         c->inst_next = 0;
         c->inst_avail = 0;
         c->closed = 0;
+        c->quit_epoch = 0;
         c->nodes = c->comp_branches = c->components = c->donations = c->pushes = 0;
         c->stale = c->local_views = 0;
         for (int i = 0; i < 8; ++i) c->comp_hist[i] = 0;

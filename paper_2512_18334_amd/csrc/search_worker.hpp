@@ -55,9 +55,10 @@ __device__ __forceinline__ uint64_t uni(uint64_t x) {
 constexpr uint32_t FOR_ROWS_AHEAD = 4;
 
 template <typename Off, typename Col, typename F>
-__device__ __forceinline__ void for_rows(Off&& off, Col&& col, const uint32_t* list,
-                                         uint32_t cnt, uint32_t* MK, F&& f) {
+__device__ __forceinline__ uint32_t for_rows(Off&& off, Col&& col, const uint32_t* list,
+                                             uint32_t cnt, uint32_t* MK, F&& f) {
     const uint32_t l = lane();
+    uint32_t entries = 0;  // CSR entries visited (wave-uniform)
     for (uint32_t base = 0; base < cnt; base += 64) {
         uint32_t i = base + l;
         uint32_t v = 0, r0 = 0, len = 0;
@@ -71,6 +72,7 @@ __device__ __forceinline__ void for_rows(Off&& off, Col&& col, const uint32_t* l
         const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
         const uint32_t delta = r0 - excl;  // CSR position of flat entry t is t + delta
         uint32_t carry = 0;                // (lane + 1) of the row running into the chunk
+        entries += total;
         for (uint32_t g0 = 0; g0 < total; g0 += 64u * FOR_ROWS_AHEAD) {
             uint32_t vv[FOR_ROWS_AHEAD], ee[FOR_ROWS_AHEAD], ww[FOR_ROWS_AHEAD];
             bool okk[FOR_ROWS_AHEAD];
@@ -103,6 +105,7 @@ __device__ __forceinline__ void for_rows(Off&& off, Col&& col, const uint32_t* l
                 if (g0 + 64u * k < total) f(okk[k], vv[k], ww[k]);
         }
     }
+    return entries;
 }
 
 // slot header word 7
@@ -278,10 +281,33 @@ struct Worker {
     __device__ __forceinline__ void load_view(int v) {
         if (v == view) return;
         if (v == 0 && !A.batch) {
-            vlds = false;
-            goff = A.off;
-            gcol = A.col;
+            // the root's induced subgraph: written before the launch and
+            // never changed, so it is copied into the cache with plain
+            // loads, eight per lane in flight, when it fits
             vn = A.n;
+            const uint32_t words = vn + 1u + A.nnz;
+            if (!(A.flags & VC_OPT_NO_ROOT_CACHE) && words <= A.gcache_words) {
+                for (uint32_t i0 = 0; i0 < words; i0 += 64u * 8u) {
+                    uint32_t x[8];
+#pragma unroll
+                    for (uint32_t k = 0; k < 8u; ++k) {
+                        const uint32_t i = i0 + 64u * k + lane();
+                        x[k] = i < words ? (i <= vn ? A.off[i] : A.col[i - vn - 1u]) : 0u;
+                    }
+#pragma unroll
+                    for (uint32_t k = 0; k < 8u; ++k) {
+                        const uint32_t i = i0 + 64u * k + lane();
+                        if (i < words) G[i] = x[k];
+                    }
+                }
+                wsync();
+                vlds = true;
+                GC = G + vn + 1u;
+            } else {
+                vlds = false;
+                goff = A.off;
+                gcol = A.col;
+            }
         } else {
             const uint32_t g_at = (uint32_t)reg_field(reinterpret_cast<const int*>(&A.reg[v].g_at));
             const uint32_t n = (uint32_t)reg_field(&A.reg[v].vn);
@@ -373,16 +399,13 @@ struct Worker {
             nn += popc(m);
         }
         wsync();
-        if (!vlds) {
-            // the rows (and their offsets) come from a view in HBM
-            uint32_t rl = 0;
-            for (uint32_t i = l; i < nn; i += 64) rl += vo(list[i] + 1) - vo(list[i]);
-            b_rows += 4ull * wave_sum(rl) + 8ull * nn;
-        }
-        for_rows([&](uint32_t x) { return vo(x); }, [&](uint32_t e) { return vc(e); }, list, nn, MK,
-                 [&](bool ok, uint32_t, uint32_t w) {
-            if (ok && DG::live(DG::get(deg, w))) DG::dec(deg, w);
-        });
+        const uint32_t ent =
+            for_rows([&](uint32_t x) { return vo(x); }, [&](uint32_t e) { return vc(e); }, list, nn,
+                     MK, [&](bool ok, uint32_t, uint32_t w) {
+                         if (ok && DG::live(DG::get(deg, w))) DG::dec(deg, w);
+                     });
+        // the rows (and their offsets) came from a view in HBM
+        if (!vlds) b_rows += 4ull * ent + 8ull * nn;
         wsync();
         s += (int)nn;
         return nn;
@@ -700,6 +723,7 @@ struct Worker {
     // the entry's initial cover in local ids (under its lock: a parent may be
     // reading the children's covers), and move the degree array to local ids.
     __device__ __forceinline__ void adopt_component_view() {
+        if (is_root(scope)) return;  // a root's view is fixed before the launch
         const uint32_t l = lane();
         const uint32_t size = nl;
         uint32_t dsum = 0;
@@ -860,7 +884,7 @@ struct Worker {
         if (!fresh) {
             // the published node never became visible: stop the search
             // (the slot stays taken, so nothing else reads it)
-            fail(VC_EDEVICE);
+            fail(VC_EDEVICE, FAIL_STALE_SLOT);
             return true;
         }
         if (lane() == 0) {
@@ -918,7 +942,7 @@ struct Worker {
             wl_publish(pos);
             return true;
         }
-        fail(VC_ENOMEM);
+        fail(VC_ENOMEM, FAIL_ARENA);
         return false;
     }
 
@@ -952,9 +976,9 @@ struct Worker {
         if (bot == top) bot = top = 0;
     }
 
-    __device__ __forceinline__ void fail(int code) {
+    __device__ __forceinline__ void fail(int code, int site) {
         if (lane() == 0) {
-            atomicCAS(&A.ctl->err, 0, code);
+            if (atomicCAS(&A.ctl->err, 0, code) == 0) st_relaxed(&A.ctl->err_site, site);
             st_relaxed(&A.ctl->done, 1);
         }
     }
@@ -1248,7 +1272,7 @@ struct Worker {
             if (lane() == 0) tot = add_relaxed(&A.ctl->nodes, nodes - nodes_flushed);
             tot = uni(tot) + (nodes - nodes_flushed);
             nodes_flushed = nodes;
-            if (tot > A.node_limit) fail(VC_ETIMEDOUT);
+            if (tot > A.node_limit) fail(VC_ETIMEDOUT, FAIL_NODE_LIMIT);
         }
     }
 
@@ -1429,8 +1453,10 @@ struct Worker {
             const int e = (int)(p + 1u + j);
             uint32_t g_at = NONE;
             // child 0 continues here and gets its own subgraph now; the
-            // others get theirs from the worker that starts them
-            if (j == 0 && size + 1u + nnz <= A.gcache_words && size < vn)
+            // others get theirs from the worker that starts them (or now,
+            // under VC_OPT_EAGER_INDUCE)
+            const bool now = j == 0 || (A.flags & VC_OPT_EAGER_INDUCE);
+            if (now && size + 1u + nnz <= A.gcache_words && size < vn)
                 g_at = induce_component(a, b, nnz, M, L);
             const bool own = g_at != NONE;
             if (l == 0)
@@ -1471,9 +1497,11 @@ struct Worker {
         cbr += 1;
         {
             // Table III: components per branch, in power-of-two buckets
+            // (constant indices only, so the counters stay in registers)
             uint32_t bk = 0;
             while (bk < 7u && (2u << bk) < nt) ++bk;
-            ++chist[bk];
+#pragma unroll
+            for (uint32_t i = 0; i < 8u; ++i) chist[i] += i == bk ? 1u : 0u;
         }
         comps += nt;
         // children 1..nt-1 go out as nodes holding only their component,
@@ -1991,7 +2019,7 @@ struct Worker {
                 if (top >= (int)NV) {
                     // cannot happen: every pending entry took a vertex out of
                     // the path's live set
-                    fail(VC_EDEVICE);
+                    fail(VC_EDEVICE, FAIL_SMALL_STACK);
                     return SMALL_STOP;
                 }
                 uint64_t nbv[W];
@@ -2162,6 +2190,13 @@ struct Worker {
                 // sees zero outstanding work while an instance is claimed
                 add_relaxed(&A.ctl->outstanding, 1);
                 uint32_t cur = ld_relaxed(&A.ctl->inst_next);
+                if (A.serve) {
+                    // a served launch that is ending claims nothing more
+                    // (the next launch does); the count above is seen by
+                    // every worker that sees the end after this check
+                    fence_seq();
+                    if (ld_relaxed(&A.ctl->quit_epoch) == A.launch_epoch) cur = limit;
+                }
                 while (cur < limit) {
                     const uint32_t prev = atomicCAS(&A.ctl->inst_next, cur, cur + 1u);
                     if (prev != cur) {
@@ -2243,7 +2278,7 @@ struct Worker {
                 if (lane() == 0) add_relaxed(&A.ctl->idle, 1);
                 uint32_t spins = 0;
                 bool got = false, quit = false, claimed = false;
-                uint64_t t_idle = wall_clock64();
+                uint64_t t_idle = wall_clock64(), t_empty = 0;
                 // poll the queue tail only; head, the outstanding count and
                 // the stop flag are read when it moved or every 16th round
                 uint64_t seen_tail = ~0ull;
@@ -2253,11 +2288,15 @@ struct Worker {
                     t = uni(t);
                     if (t != seen_tail || (round & 15u) == 0) {
                         seen_tail = t;
-                        int d = 0, outst = 0, closed = 0;
+                        int d = 0, outst = 0, closed = 0, ending = 0;
                         uint64_t h = 0;
                         uint32_t avail = 0, next = 0;
                         if (lane() == 0) {
                             d = ld_relaxed(&A.ctl->done);
+                            if (A.serve) {
+                                ending = ld_relaxed(&A.ctl->quit_epoch) == A.launch_epoch;
+                                fence_seq();
+                            }
                             h = ld_relaxed(&A.ctl->wl_head);
                             outst = ld_relaxed(&A.ctl->outstanding);
                             if (A.serve) {
@@ -2272,6 +2311,7 @@ struct Worker {
                         closed = uni(closed);
                         avail = uni(avail);
                         next = uni(next);
+                        ending = uni(ending);
                         if (d) {
                             quit = true;
                             break;
@@ -2282,6 +2322,14 @@ struct Worker {
                                 break;
                             }
                             spins = 0;
+                        } else if (ending) {
+                            // the launch is ending: no new claims; leave
+                            // once no node of it is left (a worker that
+                            // claimed just before may still need help)
+                            if (outst == 0) {
+                                quit = true;
+                                break;
+                            }
                         } else if (next < avail) {
                             // a request was published: take it as a new
                             // instance (the claim counts this worker busy)
@@ -2297,12 +2345,36 @@ struct Worker {
                             break;
                         }
                         // waiting for requests while nothing is outstanding
-                        // is a served kernel's normal state
-                        if (A.serve && outst == 0) t_idle = wall_clock64();
+                        // is a served kernel's normal state, for a while:
+                        // with no node and no unclaimed request left for
+                        // linger_ticks the launch ends as a whole (every
+                        // worker leaves, none claims again), and the server
+                        // launches it again for requests published later
+                        // (so the host's side-stream work never waits on a
+                        // launch that waits on the host)
+                        if (A.serve && outst == 0 && !ending) {
+                            const uint64_t now = wall_clock64();
+                            t_idle = now;
+                            if (next >= avail) {
+                                if (t_empty == 0) {
+                                    t_empty = now;
+                                } else if (now - t_empty > A.linger_ticks) {
+                                    if (lane() == 0) {
+                                        st_relaxed(reinterpret_cast<int*>(&A.ctl->quit_epoch),
+                                                   (int)A.launch_epoch);
+                                        fence_seq();
+                                    }
+                                    quit = true;
+                                    break;
+                                }
+                            } else {
+                                t_empty = 0;
+                            }
+                        }
                     }
                     if (wall_clock64() - t_idle > A.watchdog_ticks) {
                         // waited far longer than any node takes: give up
-                        fail(VC_EDEVICE);
+                        fail(VC_EDEVICE, FAIL_WATCHDOG);
                         quit = true;
                         break;
                     }
@@ -2345,6 +2417,7 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         h->stamp = 0;
         h->view = 0;
         h->inst = 0;
+        h->flags = SLOT_COUNTED;  // the root entry's LiveNodes = 1 is this node's
         *reinterpret_cast<uint32_t*>(a.wl_slots + a.slot_bytes - 16u) = 0u;
         Ctl* c = a.ctl;
         c->wl_head = 0;
@@ -2353,6 +2426,7 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         c->idle = 0;
         c->done = 0;
         c->err = 0;
+        c->err_site = 0;
         c->reg_next = 2;  // entry 0 is the root scope; allocations are 2-aligned
         c->arena_next = 0;
         c->inst_next = 0;

@@ -132,6 +132,10 @@ struct Server {
     vc_status plan();
     vc_status root_bufs(uint64_t n, uint64_t nnz, RootBufs* b);
     vc_status open_resident();
+    vc_status resume_if_ended();
+    hipEvent_t kend = nullptr;  // recorded after each search launch
+    bool running = false;       // a search launch may still be running
+    uint32_t epoch = 0;         // launches so far (SearchArgs::launch_epoch)
     vc_status close_resident();
     vc_status start(Req& r);
     vc_status finish(Req& r, int state);
@@ -284,6 +288,14 @@ vc_status Server::plan() {
     a.batch = 1;
     a.serve = 1;
     a.strong_fences = (c->opts.flags & VC_OPT_STRONG_ORDER) ? 1u : 0u;
+    {
+        // an idle launch ends after 20 us (VC_SERVE_LINGER_US overrides):
+        // where the side stream shares a hardware queue with the launch,
+        // the next request's root steps wait for that end
+        const char* lu = getenv("VC_SERVE_LINGER_US");
+        const uint64_t us = lu ? strtoull(lu, nullptr, 10) : 20ull;
+        a.linger_ticks = (uint64_t)c->wall_khz * us / 1000u;
+    }
     a.inst_node_limit = c->opts.node_limit;
     HIPCHK(ensure(c->pool, stacks, (size_t)workers * depth * slot_bytes));
     HIPCHK(ensure(c->pool, wl_slots, (size_t)wl_cap * slot_bytes));
@@ -368,8 +380,11 @@ vc_status Server::open_resident() {
     std::fill(slot_req.begin(), slot_req.end(), nullptr);
     HIPCHK(launch_serve_init(a, host_cap, ks));
     HIPCHK(hipEventRecord(ready, ks));
+    a.launch_epoch = ++epoch;
     HIPCHK(launch_search(a, deg_bytes, workers, ks));
+    HIPCHK(hipEventRecord(kend, ks));
     HIPCHK(hipStreamWaitEvent(ss, ready, 0));
+    running = true;
     resident = true;
     {
         std::lock_guard<std::mutex> g(mu);
@@ -379,12 +394,35 @@ vc_status Server::open_resident() {
 }
 
 // Tell the resident launch that nothing more comes, wait for it to end.
+// The launch ended by itself (nothing to do for a while): requests
+// published since are claimed by launching it again on the same state.
+vc_status Server::resume_if_ended() {
+    if (!resident) return VC_OK;
+    if (running) {
+        const hipError_t q = hipEventQuery(kend);
+        if (q == hipErrorNotReady) return VC_OK;
+        HIPCHK(q);
+        running = false;
+    }
+    // (requests admitted after the launch ended are claimed by the next one)
+    if (active == 0) return VC_OK;
+    vc_status cs = check_done();  // also fails the active requests on an error
+    if (cs) return cs;
+    if (!resident || active == 0) return VC_OK;
+    a.launch_epoch = ++epoch;
+    HIPCHK(launch_search(a, deg_bytes, workers, ks));
+    HIPCHK(hipEventRecord(kend, ks));
+    running = true;
+    return VC_OK;
+}
+
 vc_status Server::close_resident() {
     if (!resident) return VC_OK;
     const int one = 1;
     HIPCHK(hipMemcpyAsync(&a.ctl->closed, &one, 4, hipMemcpyHostToDevice, ss));
     HIPCHK(hipStreamSynchronize(ss));
     HIPCHK(hipStreamSynchronize(ks));
+    running = false;
     Ctl h;
     HIPCHK(hipMemcpy(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
     resident = false;
@@ -757,6 +795,7 @@ void Server::loop() {
         if (resident && active) {
             if (check_done()) fail_active(VC_EDEVICE);
         }
+        if (resident && resume_if_ended()) fail_active(VC_EDEVICE);
         if (!resident && active) {
             // the launch ended with admitted instances unfinished (an
             // internal error): answer them rather than wait for ever
@@ -838,6 +877,7 @@ void server_shutdown(vc_ctx* c) {
     if (s->th.joinable()) s->th.join();
     for (DevBuf* b : s->buffers()) release(*b);
     if (s->ready) hipEventDestroy(s->ready);
+    if (s->kend) hipEventDestroy(s->kend);
     if (s->ss) hipStreamDestroy(s->ss);
     if (s->ks) hipStreamDestroy(s->ks);
     delete s;
@@ -886,7 +926,8 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
             s->c = c;
             if (hipStreamCreateWithFlags(&s->ss, hipStreamNonBlocking) != hipSuccess ||
                 hipStreamCreateWithFlags(&s->ks, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess) {
+                hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&s->kend, hipEventDisableTiming) != hipSuccess) {
                 delete s;
                 return VC_EDEVICE;
             }

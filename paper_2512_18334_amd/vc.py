@@ -31,6 +31,9 @@ VC_OPT_CROWN = 128
 VC_OPT_NO_CROWN = 256
 VC_OPT_STRONG_ORDER = 512
 VC_OPT_CHECK_REGISTRY = 1024
+VC_OPT_EAGER_INDUCE = 2048
+VC_OPT_NO_ROOT_CACHE = 4096
+VC_OPT_POISON = 8192
 VC_MIN, VC_PARAM = 0, 1
 
 CYCLE_NAMES = ["fetch", "reduce", "components", "branch", "complete", "idle"]

@@ -4,6 +4,8 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# libvc names a failed HIP call or internal check on stderr (failures only)
+os.environ.setdefault("VC_DEBUG", "1")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

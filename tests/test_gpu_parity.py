@@ -36,7 +36,15 @@ def check_protocol(stats):
 
 
 def gpu_mvc(solver, g, expected):
-    r = solver.mvc(g)
+    try:
+        r = solver.mvc(g)
+    except vc.VCError:
+        # the failed call's statistics name the stage it reached
+        try:
+            print("failed solve:", g.name, solver.stats(), flush=True)
+        except vc.VCError:
+            pass
+        raise
     assert r.size == expected, (g.name, r.size, expected)
     assert_cover(g, r.cover, size=expected)
     check_protocol(r.stats)
@@ -229,12 +237,10 @@ def test_ablation_switches_agree(solver, orc, libvc):
                 gpu_mvc(s2, hubs, exp_hubs)
 
 
-def test_no_induce_searches_the_input_graph(orc, libvc):
-    """With the root reduction and induction off the search starts from the
-    input in its own ids: nothing is forced at the root, every vertex
-    (isolated ones included) keeps its id, and answers are unchanged."""
+def pendant_graph():
+    """Blocks joined by hubs, with pendant paths (the degree-one rule fires
+    at the root) and 5 isolated vertices."""
     g0 = gg.config2_blocks_hubs(seed=31, nblocks=4, bsize=24, nhubs=2, per_block=6)
-    # pendant paths (the degree-one rule fires at the root) and 5 isolated vertices
     extra = 5
     us, vs = [], []
     for i in range(8):
@@ -242,7 +248,14 @@ def test_no_induce_searches_the_input_graph(orc, libvc):
         us += [i * 3, a]
         vs += [a, a + 1]
     eu, ev = g0.edges()
-    g = gg.from_edges(g0.n + extra + 16, np.concatenate([eu, us]), np.concatenate([ev, vs]))
+    return gg.from_edges(g0.n + extra + 16, np.concatenate([eu, us]), np.concatenate([ev, vs]))
+
+
+def test_no_induce_searches_the_input_graph(orc, libvc):
+    """With the root reduction and induction off the search starts from the
+    input in its own ids: nothing is forced at the root, every vertex
+    (isolated ones included) keeps its id, and answers are unchanged."""
+    g = pendant_graph()
     e = orc.mvc(g)["size"]
     with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000) as s0:
         r0 = gpu_mvc(s0, g, e)
@@ -254,6 +267,46 @@ def test_no_induce_searches_the_input_graph(orc, libvc):
             assert r.stats["n_kernel"] == g.n
             for k in (e - 1, e):
                 assert s.pvc(g, k).yes == (e <= k)
+
+
+def test_poisoned_buffers_change_nothing(orc, libvc):
+    """Every device buffer filled with 0xA7 bytes before use (VC_OPT_POISON):
+    no step may read memory that the call did not write.  The root node's
+    header flags were once left unwritten, and memory from earlier calls
+    made the root scope induce a view of its own (wrong answers without the
+    root rules)."""
+    graphs = [pendant_graph(), gg.config1_gnp60(3),
+              gg.config2_blocks_hubs(seed=22, nblocks=3, bsize=16, nhubs=2, per_block=5),
+              gg.disjoint_union([gg.cycle(7), gg.complete(5), gg.petersen()])]
+    exp = [orc.mvc(g)["size"] for g in graphs]
+    P = vc.VC_OPT_POISON | vc.VC_OPT_CHECK_REGISTRY
+    for flags in (0, vc.VC_OPT_NO_INDUCE, vc.VC_OPT_NO_INDUCE | vc.VC_OPT_NO_SMALL,
+                  vc.VC_OPT_EAGER_INDUCE, vc.VC_OPT_NO_ROOT_CACHE, vc.VC_OPT_CROWN):
+        with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000, flags=flags | P) as s:
+            for g, e in zip(graphs, exp):
+                gpu_mvc(s, g, e)
+                gpu_pvc_threshold(s, g, e)
+    with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000, flags=P) as s:
+        res = s.mvc_batch(graphs)
+        assert [int(x) for x in res.sizes] == exp
+        for g, e, cov in zip(graphs, exp, res.covers):
+            assert_cover(g, cov, size=e)
+
+
+def test_context_reuse_after_worklist_wrap(orc, libvc):
+    """A context keeps its worklist between calls.  With 8 slots the
+    worklist wraps many times, so slot 0 (where the next call's root node
+    goes) last held some earlier node, often a component child marked for
+    induction; each call must start from its own root node only."""
+    hubs = gg.config2_blocks_hubs(seed=21, nblocks=6, bsize=48, nhubs=3, per_block=12)
+    g = pendant_graph()
+    e_h, e_g = orc.mvc(hubs)["size"], orc.mvc(g)["size"]
+    for flags in (vc.VC_OPT_NO_INDUCE, 0):
+        with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000, worklist_cap=8,
+                       flags=flags | vc.VC_OPT_CHECK_REGISTRY) as s:
+            for _ in range(3):
+                gpu_mvc(s, hubs, e_h)
+                gpu_mvc(s, g, e_g)
 
 
 def test_cycle_breakdown_counts_every_activity(solver, orc):

@@ -133,3 +133,27 @@ def test_invalid_request_is_answered_with_einval(solver):
     assert res["status"] == vc.VC_EINVAL and cov.size == 0
     res, cov = solver.wait(t_good, good.n)
     assert res["status"] == vc.VC_OK and res["size"] == 6
+
+
+def test_served_requests_with_many_streams_alive(libvc, orc):
+    """With many streams alive in the process, the runtime maps several of
+    them onto one hardware queue, so the server's side stream may share a
+    queue with its resident search launch.  A launch that waited for the
+    host would then wait for work queued behind itself; served launches end
+    when they run out of work, so requests still complete."""
+    import torch
+    streams = [torch.cuda.Stream(device=0) for _ in range(12)]
+    for st in streams:
+        with torch.cuda.stream(st):
+            torch.zeros(16, device="cuda:0").add_(1)
+    gs = [gg.config1_gnp60(s) for s in range(30, 42)]
+    with vc.Solver(0, node_limit=20_000_000, watchdog_ms=60_000) as s:
+        for rnd in range(3):
+            tickets = [s.submit(g) for g in gs]
+            for t, g in zip(tickets, gs):
+                res, cov = s.wait(t, g.n, timeout_s=60)
+                e = orc.mvc(g)["size"]
+                assert res["status"] == vc.VC_OK and res["size"] == e, (rnd, g.name, res)
+                assert_cover(g, cov, size=e)
+    torch.cuda.synchronize()
+    del streams
