@@ -176,7 +176,8 @@ vc_status device_validate(vc_ctx* c, const RootGraph& rg, int* sorted = nullptr)
     HIPCHK(hipMemsetAsync(c->ctr.p, 0, CTR_COUNT * 4, c->stream));
     HIPCHK(hipMemsetAsync(c->hsum.p, 0, 8, c->stream));
     uint32_t bad = 0;
-    HIPCHK(root_validate(rg, (uint32_t*)c->ctr.p, (unsigned long long*)c->hsum.p, c->stream, &bad,
+    HIPCHK(root_validate(rg, (uint32_t*)c->ctr.p, (unsigned long long*)c->hsum.p, c->stream,
+                         c->hm->root, &bad,
                          sorted));
     return bad ? VC_EINVAL : VC_OK;
 }
@@ -262,6 +263,7 @@ vc_status root_buffers(vc_ctx* c, const RootGraph& g, RootBufs* b) {
     b->scan_tmp = (uint32_t*)c->scan_tmp.p;
     b->ctr = (uint32_t*)c->ctr.p;
     b->hsum = (unsigned long long*)c->hsum.p;
+    b->hm = c->hm->root;
     return VC_OK;
 }
 
@@ -318,10 +320,11 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     }
     uint32_t grounds = 0;
     HIPCHK(root_greedy(rg, b, s, &grounds));
-    uint32_t ghdr[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(&ghdr[0], b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&ghdr[1], b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
+    HostMail* hm = c->hm;
+    HIPCHK(hipMemcpyAsync(&hm->ghdr[0], b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hm->ghdr[1], b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    const uint32_t ghdr[2] = {hm->ghdr[0], hm->ghdr[1]};
     const uint32_t gsize = ghdr[0] + ghdr[1];  // forced + greedy
     stv.greedy_size = gsize;
     stv.root_rounds = rounds;
@@ -343,9 +346,9 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
             if (rt) return rt;
         }
         HIPCHK(root_cover(rg, b, 0, 0, nullptr, s));
-        uint32_t cnt = 0;
-        HIPCHK(hipMemcpyAsync(&cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hm->cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        const uint32_t cnt = hm->cnt;
         if (cnt != gsize) return broken("greedy cover size");
         out->size = gsize;
         out->yes = yes;
@@ -385,10 +388,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         rounds += r2;
     }
     stv.root_rounds = rounds;
-    uint32_t sroot = 0;
-    HIPCHK(hipMemcpyAsync(&sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hm->sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(c->ev[1], s));
     HIPCHK(hipStreamSynchronize(s));
+    uint32_t sroot = hm->sroot;
     stv.forced_root = sroot;
     if ((int)sroot >= best0) {
         // no cover below best0 exists
@@ -397,11 +400,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
 
     // induce the subgraph on the vertices that still have edges
     HIPCHK(root_induce_a(rg, b, s, no_induce));
-    uint32_t hdr[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(&hdr[0], b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hm->hdr[0], b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hm->hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    uint32_t np = hdr[0], dmax = hdr[1];
+    uint32_t np = hm->hdr[0], dmax = hm->hdr[1];
     // crown reductions (Sec. IV-B), each followed by the degree rules again,
     // while crowns are found: by default on large kernels only
     const uint32_t fl = c->opts.flags;
@@ -418,20 +420,22 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         uint32_t r2 = 0;
         HIPCHK(root_reduce(rg, b, best0, s, 1u << 16, &r2));
         stv.root_rounds += r2;
-        HIPCHK(hipMemcpyAsync(&sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&stv.crown_removed, b.ctr + CTR_CROWN_I, 4, hipMemcpyDeviceToHost,
+        HIPCHK(hipMemcpyAsync(&hm->sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hm->crown_removed, b.ctr + CTR_CROWN_I, 4, hipMemcpyDeviceToHost,
                               s));
         HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(hipStreamSynchronize(s));
+        sroot = hm->sroot;
+        stv.crown_removed = hm->crown_removed;
         stv.forced_root = sroot;
         if ((int)sroot >= best0) return pvc ? finish_no() : finish_with_greedy(1);
         HIPCHK(hipMemsetAsync(b.ctr + CTR_MAXDEG, 0, 4, s));  // raised by atomicMax
         HIPCHK(root_induce_a(rg, b, s, false));
-        HIPCHK(hipMemcpyAsync(&hdr[0], b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hm->hdr[0], b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hm->hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        np = hdr[0];
-        dmax = hdr[1];
+        np = hm->hdr[0];
+        dmax = hm->hdr[1];
     }
     stv.n_kernel = np;
     stv.max_degree_kernel = dmax;
@@ -447,10 +451,10 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     } else {
         const uint32_t kcol_bytes = 4u;  // the search reads 32-bit column ids
         HIPCHK(root_induce_b(rg, b, np, kcol_bytes, s));
-        uint32_t nz = 0;
-        HIPCHK(hipMemcpyAsync(&nz, b.koff + np, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hm->nz, b.koff + np, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(c->ev[2], s));
         HIPCHK(hipStreamSynchronize(s));
+        const uint32_t nz = hm->nz;
         nnzp = nz;
         stv.nnz_kernel = nnzp;
 
@@ -548,11 +552,11 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         HIPCHK(hipEventRecord(c->ev[3], s));
         HIPCHK(launch_search(a, deg_bytes, workers, s));
         HIPCHK(hipEventRecord(c->ev[4], s));
-        Ctl ctl;
-        RegEntry root;
-        HIPCHK(hipMemcpyAsync(&ctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&root, c->reg.p, sizeof(RegEntry), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hm->ctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hm->reg0, c->reg.p, sizeof(RegEntry), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        const Ctl ctl = hm->ctl;
+        const RegEntry root = hm->reg0;
         stv.tree_nodes = ctl.nodes;
         stv.component_branches = ctl.comp_branches;
         stv.components = ctl.components;
@@ -615,9 +619,9 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
 
     const uint32_t size = sroot + (uint32_t)kbest;
     HIPCHK(root_cover(rg, b, np, 1, root_bitmap, s));
-    uint32_t cnt = 0;
-    HIPCHK(hipMemcpyAsync(&cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hm->cnt, b.newid + rg.n, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    const uint32_t cnt = hm->cnt;
     // internal invariant: |cover| == size (MVC); in PVC a cover assembled
     // while components were still improving may be smaller than its bound
     if (pvc ? cnt > size : cnt != size) {
@@ -666,6 +670,19 @@ std::vector<DevBuf*> ctx_buffers(vc_ctx* c) {
         &c->b_bad,  &c->b_hs,   &c->b_cnt,   &c->b_cov};
     for (auto& b : c->en) v.push_back(&b);
     return v;
+}
+
+hipError_t host_mail(HostMail** out) {
+    void* p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, sizeof(HostMail), hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    memset(p, 0, sizeof(HostMail));
+    *out = (HostMail*)p;
+    return hipSuccess;
+}
+
+void host_mail_free(HostMail* m) {
+    if (m) hipHostFree(m);
 }
 
 void pool_reset(vc_ctx* c) {
@@ -808,6 +825,13 @@ vc_status vc_ctx_create(int device, void* stream, void* arena, uint64_t arena_by
             return VC_EDEVICE;
         }
     }
+    he = host_mail(&c->hm);
+    if (he != hipSuccess) {
+        if (getenv("VC_DEBUG"))
+            fprintf(stderr, "libvc: hipHostMalloc -> %s\n", hipGetErrorString(he));
+        vc_ctx_destroy(c);
+        return he == hipErrorOutOfMemory ? VC_ENOMEM : VC_EDEVICE;
+    }
     // the static scratch's address on this device (library set-up, once per
     // device; vc_min_static reports a failure here)
     scratch_init(device);
@@ -826,9 +850,11 @@ vc_status vc_ctx_destroy(vc_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     if (c->batch_exec) hipGraphExecDestroy(c->batch_exec);
     for (DevBuf* b : ctx_buffers(c)) release(*b);
-    if (!c->shared_events)
+    if (!c->shared_events) {
         for (auto& e : c->ev)
             if (e) hipEventDestroy(e);
+        host_mail_free(c->hm);
+    }
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     delete c;
     return VC_OK;
@@ -891,6 +917,7 @@ vc_status vc_min_static(vc_ctx* c, const vc_csr* g, uint32_t* size, uint32_t* co
         s->lds_max = c->lds_max;
         s->wall_khz = c->wall_khz;
         for (int i = 0; i < 6; ++i) s->ev[i] = c->ev[i];
+        s->hm = c->hm;
         s->shared_events = true;
         c->scratch_ctx = s;
     }

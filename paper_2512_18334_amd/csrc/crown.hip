@@ -264,7 +264,7 @@ hipError_t crown_t(const RootGraph& g, const RootBufs& b, hipStream_t st, uint32
     const uint32_t grid = c_grid(n);
     const uint32_t wgrid = c_grid(64ull * n);  // one wave per vertex
     hipError_t e;
-    uint32_t host[3] = {0, 0, 0};
+    uint32_t* host = b.hm + 8;  // pinned read-back words
 
     // ---- M1: maximal matching by mutual proposals
     hipLaunchKernelGGL(k_mm_init, dim3(grid), dim3(256), 0, st, n, mate1, mate2);

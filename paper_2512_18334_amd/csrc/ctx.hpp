@@ -128,6 +128,24 @@ namespace vc {
 struct Server;
 }
 
+namespace vc {
+// Pinned host memory for the small read-backs of a call: a copy into
+// pageable memory is staged by the runtime and can wait until every kernel
+// on the device has finished (a resident search launch included); a copy
+// into pinned memory is a plain transfer on its stream.
+struct HostMail {
+    uint32_t root[16];  // RootBufs::hm
+    uint32_t ghdr[2];
+    uint32_t hdr[2];
+    uint32_t sroot, cnt, nz, crown_removed;
+    uint32_t w[8];      // general words
+    Ctl ctl;
+    RegEntry reg0;
+};
+hipError_t host_mail(HostMail** out);
+void host_mail_free(HostMail* m);
+}  // namespace vc
+
 struct vc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -159,7 +177,8 @@ struct vc_ctx {
     // the context that vc_min_static runs on: same device, stream, events
     // and options, with its pool over the library's static scratch
     vc_ctx* scratch_ctx = nullptr;
-    bool shared_events = false;  // events belong to another context
+    bool shared_events = false;  // events (and the mailbox) belong to another context
+    vc::HostMail* hm = nullptr;  // pinned read-back words of this context's calls
     bool wait_default = false;   // own stream: device inputs wait for the default stream
 };
 

@@ -596,7 +596,7 @@ static inline uint32_t grid_for_waves(uint64_t n) {
 }
 
 hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* hsum,
-                         hipStream_t st, uint32_t* bad_host, int* sorted_host) {
+                         hipStream_t st, uint32_t* hm, uint32_t* bad_host, int* sorted_host) {
     hipError_t e;
     hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(g.n)), dim3(256), 0, st, g.n, g.nnz,
                        g.off, ctr);
@@ -610,13 +610,13 @@ hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* 
         hipLaunchKernelGGL(k_check_rows<uint32_t>, dim3(grid_for(g.n)), dim3(256), 0, st, g.n,
                            g.off, (const uint32_t*)g.col, ctr, hsum);
     if ((e = hipGetLastError())) return e;
-    unsigned long long hs = 0;
-    uint32_t uns = 1;
-    if ((e = hipMemcpyAsync(&bad, ctr + CTR_INVALID, 4, hipMemcpyDeviceToHost, st))) return e;
-    if ((e = hipMemcpyAsync(&uns, ctr + CTR_UNSORTED, 4, hipMemcpyDeviceToHost, st))) return e;
-    if ((e = hipMemcpyAsync(&hs, hsum, 8, hipMemcpyDeviceToHost, st))) return e;
+    if ((e = hipMemcpyAsync(&hm[0], ctr + CTR_INVALID, 4, hipMemcpyDeviceToHost, st))) return e;
+    if ((e = hipMemcpyAsync(&hm[1], ctr + CTR_UNSORTED, 4, hipMemcpyDeviceToHost, st))) return e;
+    if ((e = hipMemcpyAsync(&hm[2], hsum, 8, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipStreamSynchronize(st))) return e;
-    if (hs != 0) bad |= 64u;
+    bad = hm[0];
+    const uint32_t uns = hm[1];
+    if (hm[2] != 0u || hm[3] != 0u) bad |= 64u;
     *bad_host = bad;
     if (sorted_host) *sorted_host = !bad && uns == 0;
     return hipSuccess;
@@ -644,11 +644,11 @@ static hipError_t greedy_t(const RootGraph& g, const RootBufs& b, hipStream_t st
                                b.gdeg, b.addf, b.gin, live, b.ctr + CTR_GSIZE);
         }
         if ((e = hipGetLastError())) return e;
-        uint32_t live = 0;
-        if ((e = hipMemcpyAsync(&live, b.ctr + CTR_GLIVE + ((r + 3) & 1u), 4,
+        if ((e = hipMemcpyAsync(&b.hm[4], b.ctr + CTR_GLIVE + ((r + 3) & 1u), 4,
                                 hipMemcpyDeviceToHost, st)))
             return e;
         if ((e = hipStreamSynchronize(st))) return e;
+        const uint32_t live = b.hm[4];
         if (live == 0 || r > 4 * g.n + 8) {
             *rounds = r + 4;
             return hipSuccess;
@@ -689,11 +689,11 @@ static hipError_t reduce_t(const RootGraph& g, const RootBufs& b, int best0, hip
                                b.rdeg, b.newly, b.ctr, r);
         }
         if ((e = hipGetLastError())) return e;
-        uint32_t fired = 0;
-        if ((e = hipMemcpyAsync(&fired, b.ctr + CTR_FIRED + ((r - 1) & 1u), 4,
+        if ((e = hipMemcpyAsync(&b.hm[5], b.ctr + CTR_FIRED + ((r - 1) & 1u), 4,
                                 hipMemcpyDeviceToHost, st)))
             return e;
         if ((e = hipStreamSynchronize(st))) return e;
+        const uint32_t fired = b.hm[5];
         if (fired == 0 || r >= max_rounds) break;
     }
     *rounds = r;

@@ -49,10 +49,13 @@ struct RootBufs {
     uint32_t* ctr;       // [CTR_COUNT]
     unsigned long long* hsum;
     uint32_t* cw = nullptr;  // [8n] crown workspace
+    uint32_t* hm = nullptr;  // [16] pinned host words for the steps' read-backs
 };
 
+// hm: 4 words of pinned host memory for the read-back
 hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* hsum,
-                         hipStream_t st, uint32_t* bad_host, int* sorted_host = nullptr);
+                         hipStream_t st, uint32_t* hm, uint32_t* bad_host,
+                         int* sorted_host = nullptr);
 hipError_t root_init(const RootGraph& g, const RootBufs& b, hipStream_t st);
 hipError_t root_greedy(const RootGraph& g, const RootBufs& b, hipStream_t st, uint32_t* rounds);
 // restart the greedy on the vertices the root rules left (gdeg from rdeg,

@@ -24,6 +24,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <initializer_list>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -101,6 +102,11 @@ struct Server {
     std::unordered_map<uint64_t, std::shared_ptr<Req>> table;
     std::thread th;
     bool resident_flag = false;  // a resident launch exists (read by server_busy)
+    // pinned staging of vc_submit's device-graph copies (any caller thread)
+    std::mutex sub_mu;
+    uint8_t* sub_stage = nullptr;
+    size_t sub_cap = 0;
+    std::vector<void*> old_sub;
 
     // owned by the server thread
     hipStream_t ss = nullptr, ks = nullptr;
@@ -122,6 +128,44 @@ struct Server {
     bool planned = false;
     std::vector<int> h_state;
     std::vector<uint64_t> h_nodes;
+    // read-backs go through pinned memory (a copy into pageable memory can
+    // wait for the resident launch to end): the mailbox, and a staging area
+    // for longer results (a grown one keeps the old one until shutdown)
+    HostMail* hm = nullptr;
+    uint8_t* hstage = nullptr;
+    size_t hstage_cap = 0;
+    std::vector<void*> old_pinned;
+    struct Piece {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    // copy device pieces to host memory on the side stream and wait
+    vc_status fetch(std::initializer_list<Piece> ps) {
+        size_t need = 0;
+        for (const Piece& q : ps) need += (q.bytes + 15u) & ~(size_t)15u;
+        if (need > hstage_cap) {
+            const size_t cap = std::max<size_t>(need, std::max<size_t>(2 * hstage_cap, 1u << 20));
+            void* np_ = nullptr;
+            HIPCHK(hipHostMalloc(&np_, cap, hipHostMallocDefault));
+            if (hstage) old_pinned.push_back(hstage);
+            hstage = (uint8_t*)np_;
+            hstage_cap = cap;
+        }
+        size_t at = 0;
+        for (const Piece& q : ps) {
+            if (q.bytes)
+                HIPCHK(hipMemcpyAsync(hstage + at, q.src, q.bytes, hipMemcpyDeviceToHost, ss));
+            at += (q.bytes + 15u) & ~(size_t)15u;
+        }
+        HIPCHK(hipStreamSynchronize(ss));
+        at = 0;
+        for (const Piece& q : ps) {
+            if (q.bytes) memcpy(q.dst, hstage + at, q.bytes);
+            at += (q.bytes + 15u) & ~(size_t)15u;
+        }
+        return VC_OK;
+    }
 
     std::vector<DevBuf*> buffers() {
         return {&in_off, &in_col, &rdeg,   &gdeg,     &gin,    &addf,  &newly, &flags,
@@ -154,8 +198,10 @@ struct Server {
         if (t - last_still_check < 20.0) return VC_OK;
         last_still_check = t;
         Ctl h{};
-        HIPCHK(hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ss));
-        HIPCHK(hipStreamSynchronize(ss));
+        {
+            const vc_status fs = fetch({{&h, a.ctl, sizeof(Ctl)}});
+            if (fs) return fs;
+        }
         const bool quiet = h.outstanding == 0 && h.wl_head == h.wl_tail &&
                            h.inst_next >= h.inst_avail && h.nodes == still_nodes;
         still_nodes = h.nodes;
@@ -188,9 +234,7 @@ struct Server {
         if (t - last_dump < 5000.0) return;
         last_dump = t;
         Ctl h{};
-        if (hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ss) != hipSuccess ||
-            hipStreamSynchronize(ss) != hipSuccess)
-            return;
+        if (fetch({{&h, a.ctl, sizeof(Ctl)}})) return;
         debug_dump_now(h);
     }
     void debug_dump_now(const Ctl& h) {
@@ -205,9 +249,7 @@ struct Server {
             auto& p = slot_req[i];
             if (!p || p->done) continue;
             RegEntry e{};
-            if (hipMemcpyAsync(&e, a.reg + i, sizeof(e), hipMemcpyDeviceToHost, ss) != hipSuccess ||
-                hipStreamSynchronize(ss) != hipSuccess)
-                return;
+            if (fetch({{&e, a.reg + i, sizeof(e)}})) return;
             fprintf(stderr,
                     "libvc serve:   slot %u ticket %llu kind %d n %u np %u state %d nodes %llu "
                     "live %d best %d cover %d waited %.0f ms\n",
@@ -289,11 +331,11 @@ vc_status Server::plan() {
     a.serve = 1;
     a.strong_fences = (c->opts.flags & VC_OPT_STRONG_ORDER) ? 1u : 0u;
     {
-        // an idle launch ends after 20 us (VC_SERVE_LINGER_US overrides):
-        // where the side stream shares a hardware queue with the launch,
-        // the next request's root steps wait for that end
+        // a launch with nothing left ends at once (VC_SERVE_LINGER_US sets a
+        // grace time): the root steps of requests that arrived meanwhile
+        // run between launches
         const char* lu = getenv("VC_SERVE_LINGER_US");
-        const uint64_t us = lu ? strtoull(lu, nullptr, 10) : 20ull;
+        const uint64_t us = lu ? strtoull(lu, nullptr, 10) : 0ull;
         a.linger_ticks = (uint64_t)c->wall_khz * us / 1000u;
     }
     a.inst_node_limit = c->opts.node_limit;
@@ -368,6 +410,7 @@ vc_status Server::root_bufs(uint64_t n, uint64_t nnz, RootBufs* b) {
     b->scan_tmp = (uint32_t*)scan_tmp.p;
     b->ctr = (uint32_t*)ctr.p;
     b->hsum = (unsigned long long*)hsum.p;
+    b->hm = hm->root;
     return VC_OK;
 }
 
@@ -380,11 +423,10 @@ vc_status Server::open_resident() {
     std::fill(slot_req.begin(), slot_req.end(), nullptr);
     HIPCHK(launch_serve_init(a, host_cap, ks));
     HIPCHK(hipEventRecord(ready, ks));
-    a.launch_epoch = ++epoch;
-    HIPCHK(launch_search(a, deg_bytes, workers, ks));
-    HIPCHK(hipEventRecord(kend, ks));
     HIPCHK(hipStreamWaitEvent(ss, ready, 0));
-    running = true;
+    // the search itself is launched once requests are admitted
+    // (resume_if_ended)
+    running = false;
     resident = true;
     {
         std::lock_guard<std::mutex> g(mu);
@@ -424,7 +466,10 @@ vc_status Server::close_resident() {
     HIPCHK(hipStreamSynchronize(ks));
     running = false;
     Ctl h;
-    HIPCHK(hipMemcpy(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    {
+        const vc_status fs = fetch({{&h, a.ctl, sizeof(Ctl)}});
+        if (fs) return fs;
+    }
     resident = false;
     {
         std::lock_guard<std::mutex> g(mu);
@@ -497,7 +542,7 @@ vc_status Server::start(Req& r) {
         // the checks vc_validate applies to a device graph (kernels; the
         // symmetry test by a 64-bit hash of the unordered pairs)
         uint32_t bad = 0;
-        HIPCHK(root_validate(rg, b.ctr, b.hsum, ss, &bad));
+        HIPCHK(root_validate(rg, b.ctr, b.hsum, ss, hm->root, &bad));
         if (bad) {
             r.res.status = VC_EINVAL;
             return VC_OK;
@@ -514,19 +559,19 @@ vc_status Server::start(Req& r) {
     uint32_t grounds = 0;
     HIPCHK(root_greedy(rg, b, ss, &grounds));
     uint32_t ghdr[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(&ghdr[0], b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipMemcpyAsync(&ghdr[1], b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipStreamSynchronize(ss));
+    {
+        const vc_status fs = fetch({{&ghdr[0], b.ctr + CTR_GSIZE, 4}, {&ghdr[1], b.ctr + CTR_SROOT, 4}});
+        if (fs) return fs;
+    }
     r.gsize = ghdr[0] + ghdr[1];  // forced + greedy
     auto list_to_host = [&](int improved, uint32_t np_, const uint32_t* bm) -> vc_status {
         HIPCHK(root_cover(rg, b, np_, improved, bm, ss));
         uint32_t cnt = 0;
-        HIPCHK(hipMemcpyAsync(&cnt, b.newid + r.n, 4, hipMemcpyDeviceToHost, ss));
-        HIPCHK(hipStreamSynchronize(ss));
+        vc_status fs = fetch({{&cnt, b.newid + r.n, 4}});
+        if (fs) return fs;
         r.cover.resize(cnt);
-        if (cnt)
-            HIPCHK(hipMemcpyAsync(r.cover.data(), b.cover, 4ull * cnt, hipMemcpyDeviceToHost, ss));
-        HIPCHK(hipStreamSynchronize(ss));
+        fs = fetch({{r.cover.data(), b.cover, 4ull * cnt}});
+        if (fs) return fs;
         r.res.cover_len = cnt;
         return VC_OK;
     };
@@ -540,8 +585,10 @@ vc_status Server::start(Req& r) {
     const int best0 = pvc ? (int)kq + 1 : (int)r.gsize;
     uint32_t rounds = 0;
     HIPCHK(root_reduce(rg, b, best0, ss, 1u << 16, &rounds));
-    HIPCHK(hipMemcpyAsync(&r.sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipStreamSynchronize(ss));
+    {
+        const vc_status fs = fetch({{&r.sroot, b.ctr + CTR_SROOT, 4}});
+        if (fs) return fs;
+    }
     if ((int)r.sroot >= best0) {
         if (pvc) return VC_OK;  // no
         r.res.size = r.gsize;
@@ -550,9 +597,10 @@ vc_status Server::start(Req& r) {
     }
     HIPCHK(root_induce_a(rg, b, ss));
     uint32_t hdr[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(&hdr[0], b.newid + r.n, 4, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipMemcpyAsync(&hdr[1], b.ctr + CTR_MAXDEG, 4, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipStreamSynchronize(ss));
+    {
+        const vc_status fs = fetch({{&hdr[0], b.newid + r.n, 4}, {&hdr[1], b.ctr + CTR_MAXDEG, 4}});
+        if (fs) return fs;
+    }
     r.np = hdr[0];
     r.dmax = hdr[1];
     r.kbest0 = best0 - (int)r.sroot;
@@ -565,10 +613,11 @@ vc_status Server::start(Req& r) {
     }
     HIPCHK(root_induce_b(rg, b, r.np, 4, ss));
     uint32_t nz = 0;
-    HIPCHK(hipMemcpyAsync(&nz, b.koff + r.np, 4, hipMemcpyDeviceToHost, ss));
     HIPCHK(root_cover(rg, b, 0, 1, nullptr, ss));
-    HIPCHK(hipMemcpyAsync(&r.nforced, b.newid + r.n, 4, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipStreamSynchronize(ss));
+    {
+        const vc_status fs = fetch({{&nz, b.koff + r.np, 4}, {&r.nforced, b.newid + r.n, 4}});
+        if (fs) return fs;
+    }
     r.nnzp = nz;
     // footprint in the running launch: the induced graph in the arena, the
     // forced list, the greedy list and the id map in the pool
@@ -655,8 +704,10 @@ vc_status Server::start(Req& r) {
 // The result of admitted request r from its root entry (state: its bits).
 vc_status Server::finish(Req& r, int state) {
     RegEntry e;
-    HIPCHK(hipMemcpyAsync(&e, a.reg + r.slot, sizeof(e), hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipStreamSynchronize(ss));
+    {
+        const vc_status fs = fetch({{&e, a.reg + r.slot, sizeof(e)}});
+        if (fs) return fs;
+    }
     r.res.tree_nodes = h_nodes[r.slot];
     if (r.canceled) {
         r.res.status = VC_ECANCELED;
@@ -676,9 +727,10 @@ vc_status Server::finish(Req& r, int state) {
         r.res.yes = 1;
         r.cover.resize(r.gsize);
         const uint32_t* gl = (const uint32_t*)pool.p + r.save_at + r.nforced;
-        if (r.gsize)
-            HIPCHK(hipMemcpyAsync(r.cover.data(), gl, 4ull * r.gsize, hipMemcpyDeviceToHost, ss));
-        HIPCHK(hipStreamSynchronize(ss));
+        {
+            const vc_status fs = fetch({{r.cover.data(), gl, 4ull * r.gsize}});
+            if (fs) return fs;
+        }
         r.res.cover_len = r.gsize;
         return VC_OK;
     }
@@ -701,11 +753,11 @@ vc_status Server::finish(Req& r, int state) {
                        b.cover);
     HIPCHK(hipGetLastError());
     uint32_t cnt = 0;
-    HIPCHK(hipMemcpyAsync(&cnt, b.newid + r.n, 4, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipStreamSynchronize(ss));
+    vc_status fs = fetch({{&cnt, b.newid + r.n, 4}});
+    if (fs) return fs;
     r.cover.resize(cnt);
-    if (cnt) HIPCHK(hipMemcpyAsync(r.cover.data(), b.cover, 4ull * cnt, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipStreamSynchronize(ss));
+    fs = fetch({{r.cover.data(), b.cover, 4ull * cnt}});
+    if (fs) return fs;
     r.res.cover_len = cnt;
     r.res.yes = 1;
     r.res.size = pvc ? cnt : r.sroot + (uint32_t)e.best;
@@ -717,11 +769,13 @@ vc_status Server::finish(Req& r, int state) {
 // Read the instances' state; finish those that are answered.
 vc_status Server::check_done() {
     if (!published || !active) return VC_OK;
-    HIPCHK(hipMemcpyAsync(h_state.data(), a.inst_state, 4ull * published, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipMemcpyAsync(h_nodes.data(), a.inst_nodes, 8ull * published, hipMemcpyDeviceToHost, ss));
     int ctl_done[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(ctl_done, &a.ctl->done, 8, hipMemcpyDeviceToHost, ss));
-    HIPCHK(hipStreamSynchronize(ss));
+    {
+        const vc_status fs = fetch({{h_state.data(), a.inst_state, 4ull * published},
+                                    {h_nodes.data(), a.inst_nodes, 8ull * published},
+                                    {ctl_done, &a.ctl->done, 8}});
+        if (fs) return fs;
+    }
     for (uint32_t i = 0; i < published; ++i) {
         auto& p = slot_req[i];
         if (!p || p->done) continue;
@@ -795,7 +849,6 @@ void Server::loop() {
         if (resident && active) {
             if (check_done()) fail_active(VC_EDEVICE);
         }
-        if (resident && resume_if_ended()) fail_active(VC_EDEVICE);
         if (!resident && active) {
             // the launch ended with admitted instances unfinished (an
             // internal error): answer them rather than wait for ever
@@ -804,31 +857,53 @@ void Server::loop() {
             fail_active(VC_EDEVICE);
             progress = true;
         }
-        if (!queue.empty()) {
+        // Requests start between launches: while no search launch runs, the
+        // root steps of the queued requests run one after another and the
+        // ones they do not decide are admitted; then one launch searches
+        // them all.  (Root steps issued while a launch runs were measured to
+        // wait for its end, so they are not issued then.)
+        bool busy = false;
+        if (resident && running) {
+            const hipError_t q = hipEventQuery(kend);
+            busy = q == hipErrorNotReady;
+        }
+        for (uint32_t taken = 0; !busy && taken < 64u; ++taken) {
+            {
+                // requests that arrived during the last root steps join
+                std::lock_guard<std::mutex> g(mu);
+                while (!incoming.empty()) {
+                    queue.push_back(incoming.front());
+                    incoming.pop_front();
+                }
+                if (stop)
+                    for (auto& q : queue) q->canceled = true;
+            }
+            if (queue.empty()) break;
             auto r = queue.front();
             if (r->canceled) {
                 queue.pop_front();
                 r->res.status = VC_ECANCELED;
                 complete(*r);
                 progress = true;
-            } else {
-                const vc_status s = start(*r);
-                if (s == VC_EAGAIN) {
-                    // waits for room; a launch with nothing active is closed
-                    // so the next one starts empty
-                    if (resident && active == 0) {
-                        close_resident();
-                        progress = true;
-                    }
-                } else {
-                    queue.pop_front();
-                    progress = true;
-                    if (s) r->res.status = s;
-                    if (r->admitted && !s) slot_req[r->slot] = r;
-                    else complete(*r);
-                }
+                continue;
             }
+            const vc_status s = start(*r);
+            if (s == VC_EAGAIN) {
+                // waits for room; a launch with nothing active is closed
+                // so the next one starts empty
+                if (resident && active == 0) {
+                    close_resident();
+                    progress = true;
+                }
+                break;
+            }
+            queue.pop_front();
+            progress = true;
+            if (s) r->res.status = s;
+            if (r->admitted && !s) slot_req[r->slot] = r;
+            else complete(*r);
         }
+        if (resident && resume_if_ended()) fail_active(VC_EDEVICE);
         if (resident && active == 0 && queue.empty()) {
             // nothing left: end the resident launch after a short grace
             if (idle_since == 0) idle_since = now_ms();
@@ -880,6 +955,11 @@ void server_shutdown(vc_ctx* c) {
     if (s->kend) hipEventDestroy(s->kend);
     if (s->ss) hipStreamDestroy(s->ss);
     if (s->ks) hipStreamDestroy(s->ks);
+    host_mail_free(s->hm);
+    for (void* p : s->old_pinned) hipHostFree(p);
+    if (s->hstage) hipHostFree(s->hstage);
+    for (void* p : s->old_sub) hipHostFree(p);
+    if (s->sub_stage) hipHostFree(s->sub_stage);
     delete s;
     c->srv = nullptr;
 }
@@ -904,19 +984,6 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
     r->col_bytes = g->col_bytes;
     r->off.resize((size_t)g->n + 1);
     r->col.resize((size_t)g->col_bytes * g->nnz);
-    // the request keeps its own copy: the caller may free the graph now
-    if (g->flags & VC_CSR_DEVICE) {
-        if (hipMemcpy(r->off.data(), g->offsets, 4ull * (g->n + 1), hipMemcpyDeviceToHost) !=
-            hipSuccess)
-            return VC_EDEVICE;
-        if (g->nnz && hipMemcpy(r->col.data(), g->cols, r->col.size(), hipMemcpyDeviceToHost) !=
-                          hipSuccess)
-            return VC_EDEVICE;
-    } else {
-        memcpy(r->off.data(), g->offsets, 4ull * (g->n + 1));
-        if (g->nnz) memcpy(r->col.data(), g->cols, r->col.size());
-    }
-    r->t_submit = now_ms();
     static std::mutex create_mu;
     {
         std::lock_guard<std::mutex> cg(create_mu);
@@ -927,8 +994,9 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
             if (hipStreamCreateWithFlags(&s->ss, hipStreamNonBlocking) != hipSuccess ||
                 hipStreamCreateWithFlags(&s->ks, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&s->kend, hipEventDisableTiming) != hipSuccess) {
-                delete s;
+                hipEventCreateWithFlags(&s->kend, hipEventDisableTiming) != hipSuccess ||
+                host_mail(&s->hm) != hipSuccess) {
+                delete s;  // (a partly made server keeps its handles: rare, small)
                 return VC_EDEVICE;
             }
             c->srv = s;
@@ -936,6 +1004,37 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
         }
     }
     Server* s = c->srv;
+    // the request keeps its own copy: the caller may free the graph now.  A
+    // device graph is read after the work queued before on the caller's
+    // stream (the default stream when the context has its own), through
+    // pinned staging memory.
+    if (g->flags & VC_CSR_DEVICE) {
+        std::lock_guard<std::mutex> sg(s->sub_mu);
+        const size_t ob = 4ull * (g->n + 1), cb = r->col.size();
+        const size_t need = ((ob + 15u) & ~(size_t)15u) + cb;
+        if (need > s->sub_cap) {
+            void* np_ = nullptr;
+            const size_t cap = std::max<size_t>(need, std::max<size_t>(2 * s->sub_cap, 1u << 20));
+            if (hipHostMalloc(&np_, cap, hipHostMallocDefault) != hipSuccess) return VC_ENOMEM;
+            if (s->sub_stage) s->old_sub.push_back(s->sub_stage);
+            s->sub_stage = (uint8_t*)np_;
+            s->sub_cap = cap;
+        }
+        hipStream_t cs = c->own_stream ? nullptr : c->stream;
+        uint8_t* st0 = s->sub_stage;
+        uint8_t* st1 = st0 + ((ob + 15u) & ~(size_t)15u);
+        if (hipMemcpyAsync(st0, g->offsets, ob, hipMemcpyDeviceToHost, cs) != hipSuccess)
+            return VC_EDEVICE;
+        if (cb && hipMemcpyAsync(st1, g->cols, cb, hipMemcpyDeviceToHost, cs) != hipSuccess)
+            return VC_EDEVICE;
+        if (hipStreamSynchronize(cs) != hipSuccess) return VC_EDEVICE;
+        memcpy(r->off.data(), st0, ob);
+        if (cb) memcpy(r->col.data(), st1, cb);
+    } else {
+        memcpy(r->off.data(), g->offsets, 4ull * (g->n + 1));
+        if (g->nnz) memcpy(r->col.data(), g->cols, r->col.size());
+    }
+    r->t_submit = now_ms();
     std::lock_guard<std::mutex> gl(s->mu);
     if (s->stop) return VC_ECANCELED;
     r->ticket = s->next_ticket++;
