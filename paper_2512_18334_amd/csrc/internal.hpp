@@ -110,6 +110,8 @@ enum : int {
     INST_STOP = 1,    // answered (PVC yes) or over its node limit: drop its nodes
     INST_LIMIT = 2,   // the node limit was reached
     INST_FIN = 4,     // no node of the instance is left
+    INST_GREEDY = 8,  // serving: admitted without root steps; the claiming
+                      // worker takes its bound from the rules and a greedy dive
 };
 
 struct SearchArgs {

@@ -2181,6 +2181,7 @@ struct Worker {
     __device__ __forceinline__ bool claim_instance() {
         if (!A.batch) return false;
         uint32_t got = NONE;
+        int got_state = 0;
         if (lane() == 0) {
             // instances 0 .. limit-1 exist: all of a batch, the published
             // ones when serving
@@ -2204,8 +2205,10 @@ struct Worker {
                         continue;
                     }
                     // instances answered during set-up have no root node
-                    if (!(ld_relaxed(&A.inst_state[cur]) & INST_FIN)) {
+                    const int st_ = ld_relaxed(&A.inst_state[cur]);
+                    if (!(st_ & INST_FIN)) {
                         got = cur;
+                        got_state = st_;
                         break;
                     }
                     cur = ld_relaxed(&A.ctl->inst_next);
@@ -2214,6 +2217,7 @@ struct Worker {
             }
         }
         got = uni(got);
+        got_state = uni(got_state);
         if (got == NONE) return false;
         set_inst(got);
         load_view((int)got);
@@ -2223,7 +2227,10 @@ struct Worker {
         s = 0;
         scope = (int)got;
         begin_node(NONE);
-        if (!A.serve) greedy_bound();
+        // a batch instance, or a request served as it was given, takes its
+        // first bound here; other served requests bring one from their
+        // root steps
+        if (!A.serve || (got_state & INST_GREEDY)) greedy_bound();
         return true;
     }
 

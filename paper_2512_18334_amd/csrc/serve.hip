@@ -80,6 +80,7 @@ struct Req {
     uint64_t save_at = 0;  // pool words: forced list, greedy list, new -> old ids
     uint32_t slot = 0;
     bool admitted = false, cancel_sent = false;
+    bool raw = false;  // admitted as given (no root steps; INST_GREEDY)
     // outcome
     std::atomic<bool> canceled{false};
     bool done = false;
@@ -89,6 +90,11 @@ struct Req {
 };
 
 }  // namespace
+
+// Requests of at most this many vertices go to the resident search as they
+// are (INST_GREEDY); larger ones take the root steps on the side stream,
+// whose reductions run over the whole chip.
+constexpr uint32_t RAW_N_MAX = 4096;
 
 struct Server {
     vc_ctx* c = nullptr;
@@ -182,6 +188,8 @@ struct Server {
     uint32_t epoch = 0;         // launches so far (SearchArgs::launch_epoch)
     vc_status close_resident();
     vc_status start(Req& r);
+    vc_status admit(Req& r, const uint32_t* gcsr, uint64_t words, const uint32_t* save,
+                    uint64_t save_words);
     vc_status finish(Req& r, int state);
     vc_status check_done();
     double last_dump = 0;
@@ -528,6 +536,49 @@ vc_status Server::start(Req& r) {
     }
     // no free instance slot in the running launch: wait for it to drain
     if (resident && published >= a.n_roots) return VC_EAGAIN;
+    {
+        // A request that fits the resident search as it is goes in without
+        // root steps: the worker that claims it runs the degree rules and a
+        // greedy dive for its first bound, as for a batch's instances (no
+        // side-stream work, so it is admitted at once)
+        vc_status ps0 = plan();
+        if (ps0) return ps0;
+        const uint64_t words = ((uint64_t)r.n + 1 + r.nnz + 31) & ~31ull;
+        if (r.n <= a.n && r.n <= RAW_N_MAX && words <= host_cap) {
+            if (check) {
+                const vc_status vs = validate_host(&g);
+                if (vs) {
+                    r.res.status = vs;
+                    return VC_OK;
+                }
+            }
+            // the cover is assembled in the root step buffers: sized once
+            // for every request of this path (they do not grow while a
+            // launch is open)
+            RootBufs rb;
+            const vc_status bs = root_bufs(std::max<uint64_t>(r.n, RAW_N_MAX), 0, &rb);
+            if (bs) return bs;
+            std::vector<uint32_t> csr((size_t)words, 0u);
+            memcpy(csr.data(), r.off.data(), 4ull * (r.n + 1));
+            uint32_t* cc = csr.data() + r.n + 1;
+            if (r.col_bytes == 2) {
+                const uint16_t* c16 = (const uint16_t*)r.col.data();
+                for (uint64_t e = 0; e < r.nnz; ++e) cc[e] = c16[e];
+            } else {
+                memcpy(cc, r.col.data(), 4ull * r.nnz);
+            }
+            std::vector<uint32_t> ids(r.n);
+            for (uint32_t v = 0; v < r.n; ++v) ids[v] = v;
+            r.raw = true;
+            r.np = r.n;
+            r.nnzp = r.nnz;
+            r.sroot = r.nforced = r.gsize = 0;
+            const int pvc = r.kind == VC_PARAM;
+            const uint32_t kq = std::min<uint32_t>(r.k, 0x3FFFFFF0u);
+            r.kbest0 = pvc ? (int)kq + 1 : (int)r.n;
+            return admit(r, csr.data(), words, ids.data(), r.n);
+        }
+    }
     RootBufs b;
     vc_status bs = root_bufs(r.n, r.nnz, &b);
     if (bs) return bs;
@@ -701,6 +752,67 @@ vc_status Server::start(Req& r) {
     return VC_OK;
 }
 
+// Admission of request r from host data: its graph (words of off, col as
+// 32-bit ids) into the arena, save_words ids into the pool (the map from the
+// graph's vertices to the request's ids), its root entry, cleared bitmap and
+// state, then the published count.  VC_EAGAIN when the running launch has no
+// room left.
+vc_status Server::admit(Req& r, const uint32_t* gcsr, uint64_t words, const uint32_t* save,
+                        uint64_t save_words) {
+    const uint64_t pwords = (save_words + 31) & ~31ull;
+    if (resident && (host_next + words > host_cap || pool_next + pwords > pool_cap))
+        return VC_EAGAIN;
+    if (!resident && (words > host_cap || pwords > pool_cap)) return VC_ERANGE;
+    vc_status os = open_resident();
+    if (os) return os;
+    uint32_t* pool_p = (uint32_t*)pool.p;
+    r.save_at = pool_next;
+    if (save_words)
+        HIPCHK(hipMemcpyAsync(pool_p + r.save_at, save, 4ull * save_words, hipMemcpyHostToDevice,
+                              ss));
+    pool_next += pwords;
+    const uint32_t slot = published;
+    const uint64_t g_at = host_next;
+    HIPCHK(hipMemcpyAsync(a.arena + g_at, gcsr, 4ull * (r.np + 1 + r.nnzp),
+                          hipMemcpyHostToDevice, ss));
+    host_next += words;
+    RegEntry e{};
+    e.best = r.kbest0;
+    e.live = 1;
+    e.up = -1;
+    e.cover_size = INF;
+    e.size = (int)r.np;
+    e.view = (int)slot;
+    e.vn = (int)r.np;
+    e.g_at = (uint32_t)g_at;
+    e.g_nnz = (int)r.nnzp;
+    const int pvc = r.kind == VC_PARAM;
+    const uint32_t kq = std::min<uint32_t>(r.k, 0x3FFFFFF0u);
+    const int state0 = r.raw ? INST_GREEDY : 0, zero = 0;
+    const int kslot = pvc ? (int)kq - (int)r.sroot : -1;
+    const uint64_t zero64 = 0;
+    HIPCHK(hipMemcpyAsync(a.reg + slot, &e, sizeof(e), hipMemcpyHostToDevice, ss));
+    hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(256), 0, ss, a.bitmaps + (size_t)slot * a.bm_words,
+                       (uint64_t)a.bm_words);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(a.inst_state + slot, &state0, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipMemcpyAsync(a.inst_nodes + slot, &zero64, 8, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipMemcpyAsync((int*)a.inst_k + slot, &kslot, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipMemcpyAsync((int*)a.inst_cancel + slot, &zero, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    const uint32_t avail = slot + 1;
+    HIPCHK(hipMemcpyAsync(&a.ctl->inst_avail, &avail, 4, hipMemcpyHostToDevice, ss));
+    HIPCHK(hipStreamSynchronize(ss));
+    published = avail;
+    ++active;
+    r.slot = slot;
+    r.admitted = true;
+    r.t_admit = now_ms();
+    r.res.ms_queued = r.t_admit - r.t_submit;
+    slot_req[slot] = nullptr;  // set by the caller (it holds the shared pointer)
+    return VC_OK;
+}
+
 // The result of admitted request r from its root entry (state: its bits).
 vc_status Server::finish(Req& r, int state) {
     RegEntry e;
@@ -722,6 +834,11 @@ vc_status Server::finish(Req& r, int state) {
             if (pvc) return VC_OK;
         }
         if (pvc) return VC_OK;  // no
+        if (r.raw) {
+            // the worker's greedy dive attains a cover below |V| at once
+            if (!(state & INST_LIMIT)) r.res.status = VC_EDEVICE;
+            return VC_OK;
+        }
         // nothing below the greedy bound: the greedy cover is minimum
         r.res.size = r.gsize;
         r.res.yes = 1;
