@@ -93,8 +93,9 @@ struct Req {
 
 // Requests of at most this many vertices go to the resident search as they
 // are (INST_GREEDY); larger ones take the root steps on the side stream,
-// whose reductions run over the whole chip.
-constexpr uint32_t RAW_N_MAX = 4096;
+// whose reductions run over the whole chip (one wave's degree rules on a few
+// thousand vertices took longer than those steps on the served stream).
+constexpr uint32_t RAW_N_MAX = 1024;
 
 struct Server {
     vc_ctx* c = nullptr;
