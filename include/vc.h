@@ -404,16 +404,20 @@ typedef struct {
 
 /*
  * Serving (continuous batching).  vc_submit copies the graph (host or
- * device CSR) and returns at once with a ticket; a server thread of the
- * context runs the request's root reduction and induce steps on a side
- * stream and then admits its induced subgraph, by HBM footprint (an
- * instance slot and room in the graph arena), into a resident persistent
- * search kernel that is already working on the other admitted requests:
- * idle workers pick the new instance up while the others run (each request
- * is an instance as in vc_min_batch).  Requests whose root steps already
- * decide them never reach the search.  Each request is checked on the
- * device as vc_validate checks a device graph; an invalid one is answered
- * with status VC_EINVAL.  Thread-safe: vc_submit, vc_poll and
+ * device CSR; a device CSR is read after the work queued before on the
+ * context's stream, or on the default stream when the context has its own)
+ * and returns at once with a ticket.  A server thread of the context admits
+ * requests, by HBM footprint (an instance slot and room in the graph arena),
+ * into a persistent search launch that works on all admitted requests at
+ * once (each request is an instance as in vc_min_batch): idle workers pick
+ * new instances up while the others run.  A request of at most 1,024
+ * vertices is checked on the host (as vc_validate checks a host graph) and
+ * admitted as it is; the worker that claims it takes its first bound from
+ * the degree rules and a greedy dive.  A larger request first runs the root
+ * reduction and induce steps on a side stream (checked on the device as
+ * vc_validate checks a device graph), between search launches; requests
+ * those steps decide never reach the search.  An invalid request is
+ * answered with status VC_EINVAL.  Thread-safe: vc_submit, vc_poll and
  * vc_cancel may be called from any thread.  While requests are in flight no
  * other solve may run on the context (VC_EAGAIN).
  *   kind  VC_MIN or VC_PARAM (then k is the bound).
