@@ -379,6 +379,12 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     } else {
         best0 = (int)gsize;
     }
+    if (!no_induce && ghdr[0] == 0) {
+        // the greedy took nothing: the degree rules, which keep a minimum
+        // cover, left no edge, so the vertices they forced are a minimum
+        // cover (MVC = |S_root|; a PVC bound below it is a no)
+        return pvc ? finish_no() : finish_with_greedy(1);
+    }
 
     // root reduction to a fixpoint under the bound best0 (Sec. IV-B)
     // (skipped under VC_OPT_NO_INDUCE: the search starts from the input)

@@ -634,6 +634,14 @@ vc_status Server::start(Req& r) {
         r.res.size = r.gsize;
         return list_to_host(0, 0, nullptr);
     }
+    if (ghdr[0] == 0) {
+        // the greedy took nothing: the degree rules left no edge, and the
+        // vertices they forced are a minimum cover
+        if (pvc) return VC_OK;  // no: |S_root| > k
+        r.res.size = r.gsize;
+        r.res.yes = 1;
+        return list_to_host(0, 0, nullptr);
+    }
     const int best0 = pvc ? (int)kq + 1 : (int)r.gsize;
     uint32_t rounds = 0;
     HIPCHK(root_reduce(rg, b, best0, ss, 1u << 16, &rounds));
