@@ -118,7 +118,13 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
         const uint32_t end = __builtin_amdgcn_readlane(r1, last);
         bool row_uns = false;  // this lane's row is not strictly increasing
         uint32_t carry = 0, wprev = 0;
+        // the columns of the next two chunks are loaded ahead, so three
+        // loads per wave are in flight while a chunk is checked
+        uint32_t wa = start + l < end ? cl(start + l) : 0u;
+        uint32_t wb = start + 64u + l < end ? cl(start + 64u + l) : 0u;
         for (uint32_t t0 = start; t0 < end; t0 += 64u) {
+            const uint32_t e2 = t0 + 128u + l;
+            const uint32_t wc = e2 < end ? cl(e2) : 0u;
             wave_sync();  // the previous step's reads of MK are done
             MK[l] = 0u;
             wave_sync();
@@ -131,7 +137,9 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
             const uint32_t jr = own - 1u;  // lane of this entry's row
             const uint32_t e = t0 + l;
             const bool ok = e < end;
-            const uint32_t w = ok ? (uint32_t)col[e] : 0u;
+            const uint32_t w = ok ? wa : 0u;
+            wa = wb;
+            wb = wc;
             const uint32_t rv = base + jr;
             const uint32_t rs = shfl(r0, jr);
             // the entry before, in CSR order
