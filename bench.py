@@ -156,6 +156,11 @@ def roofline(stats_list, search_ms):
            "frac": achieved / HBM_PEAK_GBS,
            "traffic": t.get("hbm_bytes_per_launch") if t else None,
            "alg_bytes_per_launch": alg_bytes}
+    # copies of component subgraphs into the workers' LDS graph caches (a
+    # view is read again each time a worker switches to it): not counted
+    # as algorithmic bytes, reported beside them
+    out["view_copy_bytes_per_launch"] = sum(s.get("bytes_views", 0)
+                                            for s in stats_list) / len(stats_list)
     # the secondary view: per-node work is latency and atomic bound
     s0 = stats_list[-1]
     out["waves_per_cu"] = s0["workers"] / 256.0

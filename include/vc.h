@@ -227,6 +227,10 @@ typedef struct {
                                     components registered (Table III): 2,
                                     3-4, 5-8, 9-16, 17-32, 33-64, 65-128,
                                     more                                     */
+    uint64_t bytes_views;        /* bytes of component subgraphs (and the
+                                    root's) copied from HBM into the
+                                    workers' LDS graph caches, each time a
+                                    worker switched to another view          */
 } vc_stats;
 
 typedef struct vc_ctx vc_ctx;

@@ -573,6 +573,7 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         stv.bytes_nodes = ctl.bytes_nodes;
         stv.bytes_registry = ctl.bytes_registry;
         stv.bytes_rows = ctl.bytes_rows;
+        stv.bytes_views = ctl.bytes_views;
         for (int i = 0; i < 8; ++i) stv.comp_hist[i] = ctl.comp_hist[i];
         stv.slot_bytes = slot_bytes;
         stv.bitmap_bytes = 4u * bm_words;

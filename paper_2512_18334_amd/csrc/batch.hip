@@ -476,6 +476,7 @@ vc_status run_batch(vc_ctx* c, const vc_batch* b, int pvc, const uint32_t* k, Ba
     stv.bytes_nodes = ctl.bytes_nodes;
     stv.bytes_registry = ctl.bytes_registry;
     stv.bytes_rows = ctl.bytes_rows;
+    stv.bytes_views = ctl.bytes_views;
     for (int i = 0; i < 8; ++i) stv.comp_hist[i] = ctl.comp_hist[i];
     stv.stale_reads = ctl.stale;
     {

@@ -99,7 +99,8 @@ struct Ctl {
     uint64_t bytes_nodes;     // bytes written into node slots (each is read back once)
     uint64_t bytes_registry;  // bytes of registry entries, cover bitmaps and arena graphs written
     uint64_t bytes_rows;      // CSR bytes read from HBM for the rows of removed vertices
-    uint64_t _p7[7];
+    uint64_t bytes_views;     // view bytes copied from HBM into the LDS graph caches
+    uint64_t _p7[6];
 };
 // Device-side checks that stop a search (Ctl::err_site)
 enum { FAIL_NONE = 0, FAIL_STALE_SLOT, FAIL_ARENA, FAIL_NODE_LIMIT, FAIL_SMALL_STACK, FAIL_WATCHDOG };

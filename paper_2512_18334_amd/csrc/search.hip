@@ -154,7 +154,7 @@ __global__ void batch_init_kernel(SearchArgs a, BatchDesc d) {
         c->stale = c->local_views = 0;
         for (int i = 0; i < 8; ++i) c->comp_hist[i] = 0;
         for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
-        c->bytes_nodes = c->bytes_registry = c->bytes_rows = 0;
+        c->bytes_nodes = c->bytes_registry = c->bytes_rows = c->bytes_views = 0;
     }
 }
 
@@ -235,7 +235,7 @@ __global__ void serve_init_kernel(SearchArgs a, uint64_t host_words) {
         c->stale = c->local_views = 0;
         for (int i = 0; i < 8; ++i) c->comp_hist[i] = 0;
         for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
-        c->bytes_nodes = c->bytes_registry = c->bytes_rows = 0;
+        c->bytes_nodes = c->bytes_registry = c->bytes_rows = c->bytes_views = 0;
     }
 }
 

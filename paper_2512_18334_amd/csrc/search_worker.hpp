@@ -157,6 +157,7 @@ struct Worker {
     uint64_t t_mark;
     uint64_t b_nodes, b_reg;  // algorithmic bytes written (node slots; registry)
     uint64_t b_rows;          // CSR bytes of removed vertices' rows read from HBM views
+    uint64_t b_views;         // view bytes copied from HBM into the graph cache
     uint32_t inst;            // instance of the current node (batches)
     uint64_t inst_cnt;        // its nodes not yet added to inst_nodes
 
@@ -177,7 +178,7 @@ struct Worker {
         G = reinterpret_cast<uint32_t*>(lds + a.lds_G);
         stack = a.stacks + (size_t)blockIdx.x * a.stack_depth * a.slot_bytes;
         bot = top = 0;
-        b_nodes = b_reg = b_rows = 0;
+        b_nodes = b_reg = b_rows = b_views = 0;
         inst = 0;
         inst_cnt = 0;
         for (int i = 0; i < 6; ++i) cyc[i] = 0;
@@ -303,6 +304,7 @@ struct Worker {
                 wsync();
                 vlds = true;
                 GC = G + vn + 1u;
+                b_views += 4ull * words;
             } else {
                 vlds = false;
                 goff = A.off;
@@ -319,6 +321,7 @@ struct Worker {
                 wsync();
                 vlds = true;
                 GC = G + n + 1u;
+                b_views += 4ull * words;
             } else {
                 // an instance graph of a batch too large for the cache: read
                 // in place (written before the search started)
@@ -2171,6 +2174,7 @@ struct Worker {
             add_relaxed(&A.ctl->bytes_nodes, b_nodes);
             add_relaxed(&A.ctl->bytes_registry, b_reg);
             add_relaxed(&A.ctl->bytes_rows, b_rows);
+            add_relaxed(&A.ctl->bytes_views, b_views);
             for (int i = 0; i < 8; ++i)
                 if (chist[i]) add_relaxed(&A.ctl->comp_hist[i], chist[i]);
         }
@@ -2441,7 +2445,7 @@ __global__ void search_init_kernel(SearchArgs a, int best0, const uint32_t* kdeg
         c->stale = c->local_views = 0;
         for (int i = 0; i < 8; ++i) c->comp_hist[i] = 0;
         for (int i = 0; i < 6; ++i) c->cyc[i] = 0;
-        c->bytes_nodes = c->bytes_registry = c->bytes_rows = 0;
+        c->bytes_nodes = c->bytes_registry = c->bytes_rows = c->bytes_views = 0;
         RegEntry r = {};
         r.best = best0;
         r.live = 1;

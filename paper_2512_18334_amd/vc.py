@@ -99,7 +99,7 @@ class vc_stats(ctypes.Structure):
                 ("reg_checked", ctypes.c_uint32), ("reg_open", ctypes.c_uint32),
                 ("reg_parents", ctypes.c_uint32), ("reg_depth", ctypes.c_uint32),
                 ("lists_in_hbm", ctypes.c_uint32), ("bytes_rows", ctypes.c_uint64),
-                ("comp_hist", ctypes.c_uint32 * 8)]
+                ("comp_hist", ctypes.c_uint32 * 8), ("bytes_views", ctypes.c_uint64)]
 
 
 class VCError(RuntimeError):
