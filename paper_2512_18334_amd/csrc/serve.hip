@@ -1122,7 +1122,12 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
                 hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&s->kend, hipEventDisableTiming) != hipSuccess ||
                 host_mail(&s->hm) != hipSuccess) {
-                delete s;  // (a partly made server keeps its handles: rare, small)
+                if (s->ready) (void)hipEventDestroy(s->ready);
+                if (s->kend) (void)hipEventDestroy(s->kend);
+                if (s->ss) (void)hipStreamDestroy(s->ss);
+                if (s->ks) (void)hipStreamDestroy(s->ks);
+                host_mail_free(s->hm);
+                delete s;
                 return VC_EDEVICE;
             }
             c->srv = s;
