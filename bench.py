@@ -618,7 +618,7 @@ def bench_serve(args, torch, gg, vc):
 
 ABLATIONS = [("proposed", 0), ("no_components", 1), ("no_reduce_induce", 32),
              ("no_compaction", 64), ("no_load_balance", 2), ("no_small_solver", 16),
-             ("crown_forced", 128), ("eager_induce", 2048)]
+             ("crown_forced", 128), ("eager_induce", 2048), ("no_root_cache", 4096)]
 
 
 def bench_ablation(args, torch, gg, vc):
