@@ -172,9 +172,9 @@ constexpr uint32_t CROWN_AUTO_MIN = 4096;
 
 vc_status device_validate(vc_ctx* c, const RootGraph& rg, int* sorted = nullptr) {
     HIPCHK(ensure(c->pool, c->ctr, CTR_COUNT * 4));
-    HIPCHK(ensure(c->pool, c->hsum, 8));
+    HIPCHK(ensure(c->pool, c->hsum, 8 * HSUM_SLOTS));
     HIPCHK(hipMemsetAsync(c->ctr.p, 0, CTR_COUNT * 4, c->stream));
-    HIPCHK(hipMemsetAsync(c->hsum.p, 0, 8, c->stream));
+    HIPCHK(hipMemsetAsync(c->hsum.p, 0, 8 * HSUM_SLOTS, c->stream));
     uint32_t bad = 0;
     HIPCHK(root_validate(rg, (uint32_t*)c->ctr.p, (unsigned long long*)c->hsum.p, c->stream,
                          c->hm->root, &bad,
@@ -247,7 +247,7 @@ vc_status root_buffers(vc_ctx* c, const RootGraph& g, RootBufs* b) {
     HIPCHK(ensure(c->pool, c->cover, 4 * n1));
     HIPCHK(ensure(c->pool, c->scan_tmp, 4 * (n / 2048 + 4)));
     HIPCHK(ensure(c->pool, c->ctr, CTR_COUNT * 4));
-    HIPCHK(ensure(c->pool, c->hsum, 8));
+    HIPCHK(ensure(c->pool, c->hsum, 8 * HSUM_SLOTS));
     b->rdeg = (uint32_t*)c->rdeg.p;
     b->gdeg = (uint32_t*)c->gdeg.p;
     b->gin = (uint8_t*)c->gin.p;

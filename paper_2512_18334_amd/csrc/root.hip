@@ -185,7 +185,15 @@ __global__ void __launch_bounds__(256) k_check_rows(uint32_t n, const uint32_t* 
     if (bad) atomicOr(&ctr[CTR_INVALID], bad);
     if (ballot(uns) != 0ull && l == 0) atomicOr(&ctr[CTR_UNSORTED], 1u);
     acc = wave_sum64(acc);
-    if (l == 0 && acc) atomicAdd(hsum, (unsigned long long)acc);
+    if (l == 0 && acc) atomicAdd(&hsum[wave % HSUM_SLOTS], (unsigned long long)acc);
+}
+
+// hsum[0] = the sum of the HSUM_SLOTS partial hash sums (one wave)
+__global__ void __launch_bounds__(64) k_hsum_fold(unsigned long long* hsum) {
+    const uint32_t l = threadIdx.x;
+    uint64_t x = l < HSUM_SLOTS ? (uint64_t)hsum[l] : 0ull;
+    x = wave_sum64(x);
+    if (l == 0) hsum[0] = (unsigned long long)x;
 }
 
 // ------------------------------------------------------------- degrees
@@ -617,6 +625,7 @@ hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* 
     else
         hipLaunchKernelGGL(k_check_rows<uint32_t>, dim3(grid_for(g.n)), dim3(256), 0, st, g.n,
                            g.off, (const uint32_t*)g.col, ctr, hsum);
+    hipLaunchKernelGGL(k_hsum_fold, dim3(1), dim3(64), 0, st, hsum);
     if ((e = hipGetLastError())) return e;
     if ((e = hipMemcpyAsync(&hm[0], ctr + CTR_INVALID, 4, hipMemcpyDeviceToHost, st))) return e;
     if ((e = hipMemcpyAsync(&hm[1], ctr + CTR_UNSORTED, 4, hipMemcpyDeviceToHost, st))) return e;

@@ -52,6 +52,12 @@ struct RootBufs {
     uint32_t* hm = nullptr;  // [16] pinned host words for the steps' read-backs
 };
 
+// The row check's symmetry hash is summed over HSUM_SLOTS 64-bit words (one
+// word per wave would make every wave's atomic meet at one address); the
+// caller provides and zeroes them (hsum), and the check folds them into
+// hsum[0].
+constexpr uint32_t HSUM_SLOTS = 64;
+
 // hm: 4 words of pinned host memory for the read-back
 hipError_t root_validate(const RootGraph& g, uint32_t* ctr, unsigned long long* hsum,
                          hipStream_t st, uint32_t* hm, uint32_t* bad_host,

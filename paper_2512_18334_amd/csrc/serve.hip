@@ -402,7 +402,7 @@ vc_status Server::root_bufs(uint64_t n, uint64_t nnz, RootBufs* b) {
         HIPCHK(ensure(c->pool, cover, 4 * n1));
         HIPCHK(ensure(c->pool, scan_tmp, 4 * (n1 / 2048 + 4)));
         HIPCHK(ensure(c->pool, ctr, CTR_COUNT * 4));
-        HIPCHK(ensure(c->pool, hsum, 8));
+        HIPCHK(ensure(c->pool, hsum, 8 * HSUM_SLOTS));
     }
     b->rdeg = (uint32_t*)rdeg.p;
     b->gdeg = (uint32_t*)gdeg.p;
@@ -588,7 +588,8 @@ vc_status Server::start(Req& r) {
     HIPCHK(hipMemcpyAsync(in_col.p, r.col.data(), (size_t)r.col_bytes * r.nnz,
                           hipMemcpyHostToDevice, ss));
     hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, b.ctr, (uint64_t)CTR_COUNT);
-    hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, (uint32_t*)b.hsum, (uint64_t)2);
+    hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, (uint32_t*)b.hsum,
+                       (uint64_t)(2 * HSUM_SLOTS));
     HIPCHK(hipGetLastError());
     if (check) {
         // the checks vc_validate applies to a device graph (kernels; the
