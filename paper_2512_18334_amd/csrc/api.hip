@@ -323,11 +323,12 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
     HostMail* hm = c->hm;
     HIPCHK(hipMemcpyAsync(&hm->ghdr[0], b.ctr + CTR_GSIZE, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&hm->ghdr[1], b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hm->w[0], b.ctr + CTR_ROUNDS, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const uint32_t ghdr[2] = {hm->ghdr[0], hm->ghdr[1]};
     const uint32_t gsize = ghdr[0] + ghdr[1];  // forced + greedy
     stv.greedy_size = gsize;
-    stv.root_rounds = rounds;
+    stv.root_rounds = rounds + hm->w[0];  // (small graphs count on the device)
     stv.forced_root = ghdr[1];
 
     // answers decided at the root: the root steps' device time ends here
@@ -393,11 +394,12 @@ vc_status solve(vc_ctx* c, const vc_csr* g, int pvc, uint32_t k, Outcome* out, u
         HIPCHK(root_reduce(rg, b, best0, s, 1u << 16, &r2));
         rounds += r2;
     }
-    stv.root_rounds = rounds;
     HIPCHK(hipMemcpyAsync(&hm->sroot, b.ctr + CTR_SROOT, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hm->w[0], b.ctr + CTR_ROUNDS, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(c->ev[1], s));
     HIPCHK(hipStreamSynchronize(s));
     uint32_t sroot = hm->sroot;
+    stv.root_rounds = rounds + hm->w[0];
     stv.forced_root = sroot;
     if ((int)sroot >= best0) {
         // no cover below best0 exists

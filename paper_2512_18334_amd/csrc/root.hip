@@ -50,7 +50,8 @@ __device__ __forceinline__ void block_atomic_add(uint32_t* p, uint32_t x) {
 // stream beside its resident search, which leaves 32 KB of LDS per CU to
 // them, so none may take more than 16 KB per block (a kernel that could not
 // be placed would wait for the resident search forever); each is launched
-// with 256 threads, which its __launch_bounds__ states.
+// with 256 threads, which its __launch_bounds__ states, except the
+// one-workgroup kernels of small graphs (1,024 threads, a few words of LDS).
 constexpr uint32_t SIDE_LDS_MAX = 16384u;
 static_assert(sizeof(uint32_t) * 4u * ROWCHK_TBL <= SIDE_LDS_MAX, "k_check_rows table");
 static_assert(sizeof(uint32_t) * 4u <= SIDE_LDS_MAX, "block_atomic_add partial sums");
@@ -426,6 +427,199 @@ __global__ void __launch_bounds__(256) k_reduce_remove(uint32_t n, const uint32_
     }
 }
 
+// ------------------------------------------------------------- small graphs
+// Graphs of at most SMALL_N vertices run the rounds of the reduction, and
+// of the greedy, inside one workgroup: the phases of a round (decide, mark,
+// remove; select, apply) are separated by barriers instead of launches, and
+// the host checks nothing between rounds.  Each phase does what the kernel
+// of the same name does for the whole grid, on the same state.
+constexpr uint32_t SMALL_N = 4096;
+constexpr uint32_t SMALL_T = 1024;
+
+template <typename C>
+__global__ void __launch_bounds__(SMALL_T) k_reduce_small(uint32_t n, const uint32_t* off,
+                                                          const C* col, uint32_t* rdeg,
+                                                          uint8_t* addf, uint8_t* newly,
+                                                          uint32_t* ctr, int best0, int sorted,
+                                                          uint32_t max_rounds) {
+    __shared__ uint32_t sh_fired, sh_added;
+    __shared__ int sh_s;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t l = tid & 63u, wave = tid >> 6, waves = nt >> 6;
+    if (tid == 0) sh_s = (int)ctr[CTR_SROOT];
+    uint32_t r = 0;
+    for (; r < max_rounds; ++r) {
+        if (tid == 0) {
+            sh_fired = 0;
+            sh_added = 0;
+        }
+        __syncthreads();
+        const int s = sh_s;
+        if (s >= best0) break;
+        const int64_t bnd = (int64_t)best0 - s - 1;
+        // decide (on the state before the round)
+        uint32_t fired = 0;
+        for (uint32_t v = tid; v < n; v += nt) {
+            const uint32_t d = rdeg[v];
+            if (!rlive(d)) continue;
+            if ((int64_t)d > bnd) {
+                addf[v] = 1;
+                ++fired;
+                continue;
+            }
+            if (d > 2u) continue;
+            uint32_t u = NONE, w = NONE, got = 0;
+            for (uint32_t e = off[v]; e < off[v + 1] && got < d; ++e) {
+                const uint32_t x = (uint32_t)col[e];
+                if (rlive(rdeg[x])) {
+                    if (got == 0) u = x; else w = x;
+                    ++got;
+                }
+            }
+            if (got < d) continue;
+            if (d == 1u) {
+                if (!(rdeg[u] == 1u && u < v)) {
+                    addf[u] = 1;
+                    ++fired;
+                }
+            } else if (r_adjacent(off, col, u, w, sorted)) {
+                if (!(rdeg[u] == 2u && u < v) && !(rdeg[w] == 2u && w < v)) {
+                    addf[u] = 1;
+                    addf[w] = 1;
+                    ++fired;
+                }
+            }
+        }
+        if (fired) atomicAdd(&sh_fired, fired);
+        __syncthreads();
+        if (sh_fired == 0) break;
+        // mark
+        uint32_t added = 0;
+        for (uint32_t v = tid; v < n; v += nt) {
+            if (!addf[v]) continue;
+            addf[v] = 0;
+            if (rlive(rdeg[v])) {
+                rdeg[v] = RIN;
+                newly[v] = 1;
+                ++added;
+            }
+        }
+        if (added) atomicAdd(&sh_added, added);
+        __syncthreads();
+        if (tid == 0) sh_s += (int)sh_added;
+        // remove: a lane per marked vertex, the wave for a long row
+        for (uint32_t base = wave * 64u; base < n; base += waves * 64u) {
+            const uint32_t v = base + l;
+            const bool nw = v < n && newly[v];
+            uint32_t r0 = 0, r1 = 0;
+            if (nw) {
+                newly[v] = 0;
+                r0 = off[v];
+                r1 = off[v + 1];
+            }
+            const bool longrow = nw && r1 - r0 > 16u;
+            if (nw && !longrow) {
+                for (uint32_t e = r0; e < r1; ++e) {
+                    const uint32_t u = (uint32_t)col[e];
+                    if (rlive(rdeg[u])) atomicSub(&rdeg[u], 1u);
+                }
+            }
+            uint64_t m = ballot(longrow);
+            while (m) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1ull;
+                const uint32_t a = shfl(r0, j), b = shfl(r1, j);
+                for (uint32_t e = a + l; e < b; e += 64u) {
+                    const uint32_t u = (uint32_t)col[e];
+                    if (rlive(rdeg[u])) atomicSub(&rdeg[u], 1u);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        ctr[CTR_SROOT] = (uint32_t)sh_s;
+        ctr[CTR_ROUNDS] += r;
+    }
+}
+
+template <typename C>
+__global__ void __launch_bounds__(SMALL_T) k_greedy_small(uint32_t n, const uint32_t* off,
+                                                          const C* col, uint32_t* gdeg,
+                                                          uint8_t* sel, uint8_t* gin,
+                                                          uint32_t* ctr) {
+    __shared__ uint32_t sh_live, sh_taken;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t l = tid & 63u, wave = tid >> 6, waves = nt >> 6;
+    uint32_t total = 0;
+    for (uint32_t round = 0; round <= 4u * n + 8u; ++round) {
+        if (tid == 0) {
+            sh_live = 0;
+            sh_taken = 0;
+        }
+        __syncthreads();
+        // select: every live vertex whose (degree, lower id) beats all its
+        // live neighbours' (rows longer than 32 entries by the whole wave)
+        uint32_t live = 0;
+        for (uint32_t base = wave * 64u; base < n; base += waves * 64u) {
+            const uint32_t v = base + l;
+            const uint32_t d = v < n ? gdeg[v] : 0u;
+            const uint32_t r0 = v < n ? off[v] : 0u, r1 = v < n ? off[v + 1] : 0u;
+            const uint64_t kv = ((uint64_t)d << 32) | (uint32_t)~v;
+            const bool longrow = d != 0u && r1 - r0 > 32u;
+            bool top = d != 0u;
+            if (d != 0u) ++live;
+            if (d != 0u && !longrow) {
+                for (uint32_t e = r0; e < r1 && top; ++e) {
+                    const uint32_t u = (uint32_t)col[e];
+                    const uint32_t du = gdeg[u];
+                    if (du && (((uint64_t)du << 32) | (uint32_t)~u) > kv) top = false;
+                }
+            }
+            uint64_t m = ballot(longrow);
+            while (m) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1ull;
+                const uint32_t a = shfl(r0, j), b = shfl(r1, j);
+                const uint32_t vj = shfl(v, j), dj = shfl(d, j);
+                const uint64_t kj = ((uint64_t)dj << 32) | (uint32_t)~vj;
+                bool beaten = false;
+                for (uint32_t e = a + l; e < b; e += 64) {
+                    const uint32_t u = (uint32_t)col[e];
+                    const uint32_t du = gdeg[u];
+                    if (du && (((uint64_t)du << 32) | (uint32_t)~u) > kj) beaten = true;
+                }
+                const bool any = ballot(beaten) != 0ull;
+                if (l == j) top = !any;
+            }
+            if (top) sel[v] = 1;
+        }
+        if (live) atomicAdd(&sh_live, live);
+        __syncthreads();
+        if (sh_live == 0) break;
+        // apply: the selected vertices form an independent set
+        uint32_t taken = 0;
+        for (uint32_t v = wave; v < n; v += waves) {
+            if (!sel[v]) continue;
+            const uint32_t r1 = off[v + 1];
+            for (uint32_t e = off[v] + l; e < r1; e += 64) {
+                const uint32_t u = (uint32_t)col[e];
+                if (gdeg[u]) atomicSub(&gdeg[u], 1u);
+            }
+            if (l == 0) {
+                sel[v] = 0;
+                gin[v] = 1;
+                gdeg[v] = 0;
+                ++taken;
+            }
+        }
+        if (taken) atomicAdd(&sh_taken, taken);
+        __syncthreads();
+        total += sh_taken;
+    }
+    if (tid == 0) ctr[CTR_GSIZE] += total;
+}
+
 // ------------------------------------------------------------- scan
 // Exclusive prefix sum, three passes: per-block totals, one block scans the
 // totals, per-block scan plus its offset.  2048 items per 256-thread block.
@@ -650,6 +844,12 @@ static hipError_t greedy_t(const RootGraph& g, const RootBufs& b, hipStream_t st
                            uint32_t* rounds) {
     const C* col = (const C*)g.col;
     hipError_t e;
+    if (g.n <= SMALL_N) {
+        hipLaunchKernelGGL(k_greedy_small<C>, dim3(1), dim3(SMALL_T), 0, st, g.n, g.off, col,
+                           b.gdeg, b.addf, b.gin, b.ctr);
+        *rounds = 0;
+        return hipGetLastError();
+    }
     const uint32_t wgrid = grid_for_waves(g.n);
     for (uint32_t r = 0;; r += 4) {
         for (uint32_t j = 0; j < 4; ++j) {
@@ -689,6 +889,13 @@ static hipError_t reduce_t(const RootGraph& g, const RootBufs& b, int best0, hip
                            uint32_t max_rounds, uint32_t* rounds) {
     const C* col = (const C*)g.col;
     hipError_t e;
+    if (g.n <= SMALL_N) {
+        // (rounds are counted in ctr[CTR_ROUNDS])
+        hipLaunchKernelGGL(k_reduce_small<C>, dim3(1), dim3(SMALL_T), 0, st, g.n, g.off, col,
+                           b.rdeg, b.addf, b.newly, b.ctr, best0, g.sorted, max_rounds);
+        *rounds = 0;
+        return hipGetLastError();
+    }
     // decide and mark end with one atomic per block on a single counter:
     // at most 1024 blocks, so a round where most blocks fire does not
     // serialise thousands of them

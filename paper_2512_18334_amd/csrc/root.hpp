@@ -20,6 +20,7 @@ enum {
     CTR_CROWN_M = 14,   // crown: vertices matched by the last proposal rounds
     CTR_CROWN_H = 15,   // crown: |H| of the last crown
     CTR_CROWN_I = 16,   // crown: |I| summed over the crowns of a solve
+    CTR_ROUNDS = 17,    // reduction rounds run inside one workgroup (small graphs)
     CTR_COUNT = 24
 };
 
