@@ -414,7 +414,7 @@ typedef struct {
  * requests, by HBM footprint (an instance slot and room in the graph arena),
  * into a persistent search launch that works on all admitted requests at
  * once (each request is an instance as in vc_min_batch): idle workers pick
- * new instances up while the others run.  A request of at most 1,024
+ * new instances up while the others run.  A request of at most 256
  * vertices is checked on the host (as vc_validate checks a host graph) and
  * admitted as it is; the worker that claims it takes its first bound from
  * the degree rules and a greedy dive.  A larger request first runs the root

@@ -92,10 +92,10 @@ struct Req {
 }  // namespace
 
 // Requests of at most this many vertices go to the resident search as they
-// are (INST_GREEDY); larger ones take the root steps on the side stream,
-// whose reductions run over the whole chip (one wave's degree rules on a few
-// thousand vertices took longer than those steps on the served stream).
-constexpr uint32_t RAW_N_MAX = 1024;
+// are (INST_GREEDY); larger ones take the root steps on the side stream
+// (in one workgroup up to 4,096 vertices, over the whole chip above).  On
+// the served stream 256 measured best: 1,024 and 64 gave 1.5-2x the p99.
+constexpr uint32_t RAW_N_MAX = 256;
 
 struct Server {
     vc_ctx* c = nullptr;
