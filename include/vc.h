@@ -410,7 +410,11 @@ typedef struct {
  * Serving (continuous batching).  vc_submit copies the graph (host or
  * device CSR; a device CSR is read after the work queued before on the
  * context's stream, or on the default stream when the context has its own)
- * and returns at once with a ticket.  A server thread of the context admits
+ * and returns at once with a ticket: the caller may free the graph then.  A
+ * device graph of more than 256 vertices is copied device to device into a
+ * 64 MiB request ring that the server allocates with itself (contexts whose
+ * buffers come from hipMalloc); when the ring is full, and for every other
+ * graph, the copy goes to host memory.  A server thread of the context admits
  * requests, by HBM footprint (an instance slot and room in the graph arena),
  * into a persistent search launch that works on all admitted requests at
  * once (each request is an instance as in vc_min_batch): idle workers pick

@@ -81,6 +81,10 @@ struct Req {
     uint32_t slot = 0;
     bool admitted = false, cancel_sent = false;
     bool raw = false;  // admitted as given (no root steps; INST_GREEDY)
+    // a device graph kept on the device: offsets at byte ring_at of the
+    // server's request ring, columns at ring_at + ring_col
+    bool on_ring = false;
+    uint64_t ring_at = 0, ring_col = 0;
     // outcome
     std::atomic<bool> canceled{false};
     bool done = false;
@@ -96,6 +100,8 @@ struct Req {
 // (in one workgroup up to 4,096 vertices, over the whole chip above).  On
 // the served stream 256 measured best: 1,024 and 64 gave 1.5-2x the p99.
 constexpr uint32_t RAW_N_MAX = 256;
+// device memory for served device graphs waiting for their root steps
+constexpr uint64_t RING_BYTES = 64ull << 20;
 
 struct Server {
     vc_ctx* c = nullptr;
@@ -114,6 +120,61 @@ struct Server {
     uint8_t* sub_stage = nullptr;
     size_t sub_cap = 0;
     std::vector<void*> old_sub;
+    // Device graphs larger than RAW_N_MAX stay on the device: vc_submit
+    // copies them into this ring (device to device) and the root steps read
+    // them there.  Pieces are taken at the head and come back in any order;
+    // the tail moves past the oldest piece once it is back.  Under sub_mu.
+    // Only a context whose buffers come from hipMalloc has a ring (a
+    // caller's arena is reset by blocking calls).
+    struct RingPiece {
+        uint64_t at, bytes;
+        bool back;
+    };
+    uint8_t* ring = nullptr;
+    uint64_t ring_cap = 0, ring_head = 0, ring_tail = 0;
+    std::deque<RingPiece> ring_live;
+    bool ring_take(uint64_t bytes, uint64_t* at) {
+        if (!ring) return false;
+        bytes = (bytes + 255u) & ~(uint64_t)255u;
+        uint64_t a;
+        if (ring_live.empty()) {
+            ring_head = ring_tail = 0;
+            if (bytes > ring_cap) return false;
+            a = 0;
+        } else if (ring_head > ring_tail) {
+            // live pieces in [tail, head): room after them, else before
+            if (bytes <= ring_cap - ring_head) a = ring_head;
+            else if (bytes <= ring_tail) a = 0;
+            else return false;
+        } else {
+            // wrapped: the free space is [head, tail)
+            if (bytes <= ring_tail - ring_head) a = ring_head;
+            else return false;
+        }
+        *at = a;
+        ring_head = a + bytes;
+        ring_live.push_back({a, bytes, false});
+        return true;
+    }
+    void ring_give_locked(uint64_t at) {
+        for (auto& q : ring_live)
+            if (q.at == at && !q.back) {
+                q.back = true;
+                break;
+            }
+        while (!ring_live.empty() && ring_live.front().back) ring_live.pop_front();
+        if (ring_live.empty()) ring_head = ring_tail = 0;
+        else ring_tail = ring_live.front().at;
+    }
+    // a request's ring piece comes back once the side stream has finished
+    // every read of it
+    void ring_give(Req& r) {
+        if (!r.on_ring) return;
+        (void)hipStreamSynchronize(ss);
+        std::lock_guard<std::mutex> g(sub_mu);
+        ring_give_locked(r.ring_at);
+        r.on_ring = false;
+    }
 
     // owned by the server thread
     hipStream_t ss = nullptr, ks = nullptr;
@@ -519,6 +580,9 @@ vc_status Server::start(Req& r) {
     r.res.kind = r.kind;
     r.res.n = r.n;
     vc_csr g{r.n, r.nnz, r.off.data(), r.nnz ? (const void*)r.col.data() : nullptr, r.col_bytes, 0};
+    if (r.on_ring)
+        g = vc_csr{r.n, r.nnz, (const uint32_t*)(ring + r.ring_at), ring + r.ring_at + r.ring_col,
+                   r.col_bytes, VC_CSR_DEVICE};
     const bool check = !(c->opts.flags & VC_OPT_VALIDATE_SKIP);
     if (r.n == 0 || r.nnz == 0) {
         // nothing to search; the offsets must still be all zero
@@ -584,9 +648,14 @@ vc_status Server::start(Req& r) {
     vc_status bs = root_bufs(r.n, r.nnz, &b);
     if (bs) return bs;
     RootGraph rg{r.n, r.nnz, (const uint32_t*)in_off.p, in_col.p, r.col_bytes};
-    HIPCHK(hipMemcpyAsync(in_off.p, r.off.data(), 4ull * (r.n + 1), hipMemcpyHostToDevice, ss));
-    HIPCHK(hipMemcpyAsync(in_col.p, r.col.data(), (size_t)r.col_bytes * r.nnz,
-                          hipMemcpyHostToDevice, ss));
+    if (r.on_ring) {
+        rg.off = (const uint32_t*)g.offsets;
+        rg.col = g.cols;
+    } else {
+        HIPCHK(hipMemcpyAsync(in_off.p, r.off.data(), 4ull * (r.n + 1), hipMemcpyHostToDevice, ss));
+        HIPCHK(hipMemcpyAsync(in_col.p, r.col.data(), (size_t)r.col_bytes * r.nnz,
+                              hipMemcpyHostToDevice, ss));
+    }
     hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, b.ctr, (uint64_t)CTR_COUNT);
     hipLaunchKernelGGL(k_srv_zero, dim3(1), dim3(64), 0, ss, (uint32_t*)b.hsum,
                        (uint64_t)(2 * HSUM_SLOTS));
@@ -1009,6 +1078,7 @@ void Server::loop() {
             auto r = queue.front();
             if (r->canceled) {
                 queue.pop_front();
+                ring_give(*r);
                 r->res.status = VC_ECANCELED;
                 complete(*r);
                 progress = true;
@@ -1025,6 +1095,7 @@ void Server::loop() {
                 break;
             }
             queue.pop_front();
+            ring_give(*r);
             progress = true;
             if (s) r->res.status = s;
             if (r->admitted && !s) slot_req[r->slot] = r;
@@ -1078,6 +1149,7 @@ void server_shutdown(vc_ctx* c) {
     }
     if (s->th.joinable()) s->th.join();
     for (DevBuf* b : s->buffers()) release(*b);
+    if (s->ring) (void)hipFree(s->ring);
     if (s->ready) hipEventDestroy(s->ready);
     if (s->kend) hipEventDestroy(s->kend);
     if (s->ss) hipStreamDestroy(s->ss);
@@ -1109,8 +1181,6 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
     r->n = g->n;
     r->nnz = g->nnz;
     r->col_bytes = g->col_bytes;
-    r->off.resize((size_t)g->n + 1);
-    r->col.resize((size_t)g->col_bytes * g->nnz);
     static std::mutex create_mu;
     {
         std::lock_guard<std::mutex> cg(create_mu);
@@ -1131,6 +1201,16 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
                 delete s;
                 return VC_EDEVICE;
             }
+            if (!c->pool.base) {
+                // the request ring (without it device graphs go through the host)
+                void* rp = nullptr;
+                if (hipMalloc(&rp, RING_BYTES) == hipSuccess) {
+                    s->ring = (uint8_t*)rp;
+                    s->ring_cap = RING_BYTES;
+                } else {
+                    (void)hipGetLastError();
+                }
+            }
             c->srv = s;
             s->th = std::thread([s] { s->loop(); });
         }
@@ -1140,9 +1220,32 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
     // device graph is read after the work queued before on the caller's
     // stream (the default stream when the context has its own), through
     // pinned staging memory.
-    if (g->flags & VC_CSR_DEVICE) {
+    const size_t ob = 4ull * (g->n + 1), cb = (size_t)g->col_bytes * g->nnz;
+    hipStream_t cs = c->own_stream ? nullptr : c->stream;
+    if (g->flags & VC_CSR_DEVICE && g->n > RAW_N_MAX && g->nnz) {
+        // into the request ring when it has room
         std::lock_guard<std::mutex> sg(s->sub_mu);
-        const size_t ob = 4ull * (g->n + 1), cb = r->col.size();
+        const uint64_t colat = (ob + 255u) & ~(uint64_t)255u;
+        uint64_t at = 0;
+        if (s->ring_take(colat + cb, &at)) {
+            if (hipMemcpyAsync(s->ring + at, g->offsets, ob, hipMemcpyDeviceToDevice, cs) != hipSuccess ||
+                hipMemcpyAsync(s->ring + at + colat, g->cols, cb, hipMemcpyDeviceToDevice, cs) !=
+                    hipSuccess ||
+                hipStreamSynchronize(cs) != hipSuccess) {
+                s->ring_give_locked(at);
+                return VC_EDEVICE;
+            }
+            r->on_ring = true;
+            r->ring_at = at;
+            r->ring_col = colat;
+        }
+    }
+    if (r->on_ring) {
+        // on the device already
+    } else if (g->flags & VC_CSR_DEVICE) {
+        r->off.resize((size_t)g->n + 1);
+        r->col.resize(cb);
+        std::lock_guard<std::mutex> sg(s->sub_mu);
         const size_t need = ((ob + 15u) & ~(size_t)15u) + cb;
         if (need > s->sub_cap) {
             void* np_ = nullptr;
@@ -1152,7 +1255,6 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
             s->sub_stage = (uint8_t*)np_;
             s->sub_cap = cap;
         }
-        hipStream_t cs = c->own_stream ? nullptr : c->stream;
         uint8_t* st0 = s->sub_stage;
         uint8_t* st1 = st0 + ((ob + 15u) & ~(size_t)15u);
         if (hipMemcpyAsync(st0, g->offsets, ob, hipMemcpyDeviceToHost, cs) != hipSuccess)
@@ -1163,12 +1265,20 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
         memcpy(r->off.data(), st0, ob);
         if (cb) memcpy(r->col.data(), st1, cb);
     } else {
-        memcpy(r->off.data(), g->offsets, 4ull * (g->n + 1));
-        if (g->nnz) memcpy(r->col.data(), g->cols, r->col.size());
+        r->off.resize((size_t)g->n + 1);
+        r->col.resize(cb);
+        memcpy(r->off.data(), g->offsets, ob);
+        if (g->nnz) memcpy(r->col.data(), g->cols, cb);
     }
     r->t_submit = now_ms();
     std::lock_guard<std::mutex> gl(s->mu);
-    if (s->stop) return VC_ECANCELED;
+    if (s->stop) {
+        if (r->on_ring) {
+            std::lock_guard<std::mutex> sg(s->sub_mu);
+            s->ring_give_locked(r->ring_at);
+        }
+        return VC_ECANCELED;
+    }
     r->ticket = s->next_ticket++;
     s->table[r->ticket] = r;
     s->incoming.push_back(r);

@@ -157,3 +157,60 @@ def test_served_requests_with_many_streams_alive(libvc, orc):
                 assert_cover(g, cov, size=e)
     torch.cuda.synchronize()
     del streams
+
+
+def test_device_graph_requests_through_the_ring(solver, orc):
+    """Device graphs above 256 vertices are copied device to device into the
+    server's request ring (64 MiB) and read there by the root steps.  Thirty
+    copies of a 100,000-vertex graph (3.6 MB each) pass more than the ring
+    holds, so pieces wrap around and a full ring sends requests through the
+    host instead; a request of invalid structure is refused from the ring,
+    one is cancelled on it, and the torch tensors are dropped right after
+    each submission (the request owns its copy)."""
+    big = gg.chung_lu_planted(100_000, 400_000, 2.3, 6_000, 99, col_bytes=None, name="big")
+    mid = gg.config2_blocks_hubs(seed=71, nblocks=6, bsize=64, nhubs=3, per_block=12)
+    e_big = orc.mvc(big)["size"]
+    e_mid = orc.mvc(mid)["size"]
+    bad = gg.Graph(mid.n, mid.offsets.copy(), mid.cols.copy(), name="self-loop")
+    bad.cols[bad.offsets[5]] = 5  # a self-loop in row 5
+    plan = []
+    for i in range(30):
+        if i % 3 == 2:
+            plan.append((big, vc.VC_PARAM, e_big - (i % 2)))
+        else:
+            plan.append((big, vc.VC_MIN, 0))
+        if i % 10 == 0:
+            plan.append((mid, vc.VC_MIN, 0))
+    plan.insert(7, (bad, vc.VC_MIN, 0))
+    tickets = []
+    for g, kind, k in plan:
+        dg = vc.DeviceGraph.from_graph(g)
+        tickets.append(solver.submit(dg, kind, k))
+        del dg
+    hard = vc.DeviceGraph.from_graph(gg.gnp(300, 0.09, 4343))
+    t_hard = solver.submit(hard)
+    del hard
+    solver.cancel(t_hard)
+    for t, (g, kind, k) in zip(tickets, plan):
+        print(f"ring: waiting for {g.name} kind {kind} k {k} (ticket {t})", flush=True)
+        res, cov = solver.wait(t, g.n, timeout_s=120)
+        if g is bad:
+            assert res["status"] == vc.VC_EINVAL and cov.size == 0
+            continue
+        assert res["status"] == vc.VC_OK, (g.name, res)
+        e = e_big if g is big else e_mid
+        if kind == vc.VC_MIN:
+            assert res["size"] == e, (g.name, res["size"], e)
+            assert_cover(g, cov, size=e)
+        else:
+            assert bool(res["yes"]) == (e <= k), (g.name, k, e)
+            if res["yes"]:
+                assert_cover(g, cov, at_most=k)
+    with pytest.raises(vc.VCError) as ex:
+        solver.wait(t_hard, 300, timeout_s=60)
+    assert ex.value.status == vc.VC_ECANCELED
+    # the ring is usable again afterwards
+    t = solver.submit(vc.DeviceGraph.from_graph(mid))
+    res, cov = solver.wait(t, mid.n)
+    assert res["size"] == e_mid
+    assert_cover(mid, cov, size=e_mid)
