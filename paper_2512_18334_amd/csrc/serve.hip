@@ -249,7 +249,7 @@ struct Server {
     bool running = false;       // a search launch may still be running
     uint32_t epoch = 0;         // launches so far (SearchArgs::launch_epoch)
     vc_status close_resident();
-    vc_status start(Req& r);
+    vc_status start(Req& r, bool raw_only);
     vc_status admit(Req& r, const uint32_t* gcsr, uint64_t words, const uint32_t* save,
                     uint64_t save_words);
     vc_status finish(Req& r, int state);
@@ -574,8 +574,10 @@ void Server::fail_active(vc_status e) {
 }
 
 // Root steps of request r and, unless they decide it, its admission into
-// the resident launch.  Returns VC_EAGAIN (nothing done) when r has to wait.
-vc_status Server::start(Req& r) {
+// the resident launch.  Returns VC_EAGAIN (nothing done) when r has to wait,
+// and with raw_only (a launch is running) for every request that would need
+// root steps.
+vc_status Server::start(Req& r, bool raw_only) {
     const double t0 = now_ms();
     r.res.kind = r.kind;
     r.res.n = r.n;
@@ -644,6 +646,7 @@ vc_status Server::start(Req& r) {
             return admit(r, csr.data(), words, ids.data(), r.n);
         }
     }
+    if (raw_only) return VC_EAGAIN;
     RootBufs b;
     vc_status bs = root_bufs(r.n, r.nnz, &b);
     if (bs) return bs;
@@ -1057,13 +1060,15 @@ void Server::loop() {
         // root steps of the queued requests run one after another and the
         // ones they do not decide are admitted; then one launch searches
         // them all.  (Root steps issued while a launch runs were measured to
-        // wait for its end, so they are not issued then.)
+        // wait for its end, so they are not issued then.)  Requests that go
+        // in as given need no root steps: they join a running launch, in
+        // queue order, up to the first request that needs them.
         bool busy = false;
         if (resident && running) {
             const hipError_t q = hipEventQuery(kend);
             busy = q == hipErrorNotReady;
         }
-        for (uint32_t taken = 0; !busy && taken < 64u; ++taken) {
+        for (uint32_t taken = 0; taken < 64u; ++taken) {
             {
                 // requests that arrived during the last root steps join
                 std::lock_guard<std::mutex> g(mu);
@@ -1084,11 +1089,11 @@ void Server::loop() {
                 progress = true;
                 continue;
             }
-            const vc_status s = start(*r);
+            const vc_status s = start(*r, busy);
             if (s == VC_EAGAIN) {
                 // waits for room; a launch with nothing active is closed
                 // so the next one starts empty
-                if (resident && active == 0) {
+                if (!busy && resident && active == 0) {
                     close_resident();
                     progress = true;
                 }
