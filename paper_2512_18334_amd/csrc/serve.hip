@@ -33,6 +33,7 @@
 
 #include "ctx.hpp"
 #include "internal.hpp"
+#include "req_ring.hpp"
 #include "root.hpp"
 #include "vc.h"
 
@@ -122,50 +123,13 @@ struct Server {
     std::vector<void*> old_sub;
     // Device graphs larger than RAW_N_MAX stay on the device: vc_submit
     // copies them into this ring (device to device) and the root steps read
-    // them there.  Pieces are taken at the head and come back in any order;
-    // the tail moves past the oldest piece once it is back.  Under sub_mu.
-    // Only a context whose buffers come from hipMalloc has a ring (a
-    // caller's arena is reset by blocking calls).
-    struct RingPiece {
-        uint64_t at, bytes;
-        bool back;
-    };
+    // them there; pieces are taken in submission order and come back in any
+    // order (ReqRing).  Under sub_mu.  Only a context whose buffers come
+    // from hipMalloc has a ring (a caller's arena is reset by blocking calls).
     uint8_t* ring = nullptr;
-    uint64_t ring_cap = 0, ring_head = 0, ring_tail = 0;
-    std::deque<RingPiece> ring_live;
-    bool ring_take(uint64_t bytes, uint64_t* at) {
-        if (!ring) return false;
-        bytes = (bytes + 255u) & ~(uint64_t)255u;
-        uint64_t a;
-        if (ring_live.empty()) {
-            ring_head = ring_tail = 0;
-            if (bytes > ring_cap) return false;
-            a = 0;
-        } else if (ring_head > ring_tail) {
-            // live pieces in [tail, head): room after them, else before
-            if (bytes <= ring_cap - ring_head) a = ring_head;
-            else if (bytes <= ring_tail) a = 0;
-            else return false;
-        } else {
-            // wrapped: the free space is [head, tail)
-            if (bytes <= ring_tail - ring_head) a = ring_head;
-            else return false;
-        }
-        *at = a;
-        ring_head = a + bytes;
-        ring_live.push_back({a, bytes, false});
-        return true;
-    }
-    void ring_give_locked(uint64_t at) {
-        for (auto& q : ring_live)
-            if (q.at == at && !q.back) {
-                q.back = true;
-                break;
-            }
-        while (!ring_live.empty() && ring_live.front().back) ring_live.pop_front();
-        if (ring_live.empty()) ring_head = ring_tail = 0;
-        else ring_tail = ring_live.front().at;
-    }
+    ReqRing ring_map;
+    bool ring_take(uint64_t bytes, uint64_t* at) { return ring && ring_map.take(bytes, at); }
+    void ring_give_locked(uint64_t at) { ring_map.give(at); }
     // a request's ring piece comes back once the side stream has finished
     // every read of it
     void ring_give(Req& r) {
@@ -1211,7 +1175,7 @@ vc_status vc_submit(vc_ctx* c, const vc_csr* g, int kind, uint32_t k, uint64_t* 
                 void* rp = nullptr;
                 if (hipMalloc(&rp, RING_BYTES) == hipSuccess) {
                     s->ring = (uint8_t*)rp;
-                    s->ring_cap = RING_BYTES;
+                    s->ring_map.reset(RING_BYTES);
                 } else {
                     (void)hipGetLastError();
                 }
