@@ -280,7 +280,7 @@ def bench_blocks_hubs(args, torch, gg, vc):
         del items
         print("bench: served search-mix leg", file=sys.stderr, flush=True)
         out["serve_search_mix"] = leg_serve(args, torch, gg, vc, search_mix_items(gg, vc),
-                                            "served_gnp60_and_blocks_mix_300", calib=100)
+                                            "served_gnp60_and_blocks_mix_300")
     return out
 
 
@@ -405,14 +405,17 @@ def _wait_idle(solver, gg, vc):
             time.sleep(0.002)
 
 
-def leg_serve(args, torch, gg, vc, items, label, calib=200):
+def leg_serve(args, torch, gg, vc, items, label, calib=None):
     """A served stream at a fixed Poisson rate: 0.8 x the plain solver's
-    measured solves/s on the first `calib` requests.  p50/p99 latency and
+    measured solves/s on the first `calib` requests (all of them by default;
+    the rate taken from a 200-request prefix varied by a third between runs).  p50/p99 latency and
     solves/s, served (continuous batching) and plain first come first served
     under the same arrivals, both measured; answers compared."""
     import numpy as np
     dev = [vc.DeviceGraph.from_graph(g, "cuda:0") for g, _, _ in items]
     torch.cuda.synchronize()
+    if calib is None:
+        calib = len(items)
     with vc.Solver(0, node_limit=20_000_000, watchdog_ms=120_000) as s:
         t0 = time.perf_counter()
         for j in range(min(calib, len(items))):
