@@ -82,6 +82,7 @@ struct Req {
     uint32_t slot = 0;
     bool admitted = false, cancel_sent = false;
     bool raw = false;  // admitted as given (no root steps; INST_GREEDY)
+    bool small_rooted = false;  // at most RAW_N_MAX vertices, took the root steps
     // a device graph kept on the device: offsets at byte ring_at of the
     // server's request ring, columns at ring_at + ring_col
     bool on_ring = false;
@@ -146,6 +147,13 @@ struct Server {
     std::deque<std::shared_ptr<Req>> queue;
     std::vector<std::shared_ptr<Req>> slot_req;
     bool resident = false;
+    // how much the root steps shrink small requests: 1 for one they decide,
+    // else the share of its vertices they remove (moving average over about
+    // 16).  While no launch runs, a small request takes the root steps when
+    // they have been removing most of such graphs (every 8th one takes them
+    // anyway, to keep measuring), else it goes in as given
+    double small_root_ema = 0.5;
+    uint32_t small_seen = 0;
     uint32_t published = 0, active = 0;
     uint64_t host_next = 0, host_cap = 0, pool_next = 0, pool_cap = 0;
     double idle_since = 0;
@@ -575,7 +583,12 @@ vc_status Server::start(Req& r, bool raw_only) {
         vc_status ps0 = plan();
         if (ps0) return ps0;
         const uint64_t words = ((uint64_t)r.n + 1 + r.nnz + 31) & ~31ull;
-        if (r.n <= a.n && r.n <= RAW_N_MAX && words <= host_cap) {
+        bool go_raw = raw_only;
+        if (!raw_only && r.n <= RAW_N_MAX) {
+            const bool probe = (++small_seen & 7u) == 0;
+            go_raw = small_root_ema < 0.5 && !probe;
+        }
+        if (go_raw && r.n <= a.n && r.n <= RAW_N_MAX && words <= host_cap) {
             if (check) {
                 const vc_status vs = validate_host(&g);
                 if (vs) {
@@ -611,6 +624,7 @@ vc_status Server::start(Req& r, bool raw_only) {
         }
     }
     if (raw_only) return VC_EAGAIN;
+    r.small_rooted = r.n <= RAW_N_MAX;
     RootBufs b;
     vc_status bs = root_bufs(r.n, r.nnz, &b);
     if (bs) return bs;
@@ -1066,6 +1080,9 @@ void Server::loop() {
             queue.pop_front();
             ring_give(*r);
             progress = true;
+            if (r->small_rooted && !s && r->res.status == VC_OK)
+                small_root_ema += ((r->admitted ? 1.0 - (double)r->np / r->n : 1.0) -
+                                   small_root_ema) / 16.0;
             if (s) r->res.status = s;
             if (r->admitted && !s) slot_req[r->slot] = r;
             else complete(*r);
