@@ -419,9 +419,12 @@ typedef struct {
  * into a persistent search launch that works on all admitted requests at
  * once (each request is an instance as in vc_min_batch): idle workers pick
  * new instances up while the others run.  A request of at most 256
- * vertices is checked on the host (as vc_validate checks a host graph) and
- * admitted as it is; the worker that claims it takes its first bound from
- * the degree rules and a greedy dive.  A larger request first runs the root
+ * vertices may be checked on the host (as vc_validate checks a host graph)
+ * and admitted as it is, the worker that claims it taking its first bound
+ * from the degree rules and a greedy dive: always while a launch runs, and
+ * between launches unless the root steps have lately been removing most of
+ * the vertices of such requests (then it takes them as a larger request
+ * does).  A larger request first runs the root
  * reduction and induce steps on a side stream (checked on the device as
  * vc_validate checks a device graph), between search launches; requests
  * those steps decide never reach the search.  An invalid request is
